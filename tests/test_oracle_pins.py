@@ -1,0 +1,658 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Each test names the part of the oracle it pins and what it is checked
+against (a value printed in the paper, a closed form, a library routine, a
+conservation law, or brute force).  None of these tests touches the HIP
+path.
+"""
+import math
+
+import numpy as np
+import pytest
+from numpy.polynomial import hermite_e
+from scipy import integrate
+
+from oracle import model, step1d
+from oracle.model import Params, TERM_ADV, TERM_FORCE, TERM_J0, TERM_J1, FORCE_NONE
+from oracle.quadrature import (gauss_hermite, hermite_table, equilibrium_matrix,
+                               momentum_derivative_matrix)
+
+
+def double_factorial(k):
+    return 1 if k <= 0 else k * double_factorial(k - 2)
+
+
+# ---------------------------------------------------------------------------
+# quadrature
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("Q", [8, 16, 24])
+def test_gauss_hermite_matches_numpy(Q):
+    """Nodes/weights agree with numpy's hermegauss (a different algorithm:
+    companion-matrix roots), weights rescaled by sqrt(2 pi)."""
+    x, w = gauss_hermite(Q)
+    xr, wr = hermite_e.hermegauss(Q)
+    assert np.allclose(x, xr, rtol=0, atol=1e-13 * np.max(np.abs(xr)))
+    assert np.allclose(w, wr / math.sqrt(2 * math.pi), rtol=1e-12, atol=0)
+
+
+@pytest.mark.parametrize("Q", [8, 16, 24])
+def test_gauss_hermite_exact_moments(Q):
+    """sum_k w_k p_k^s = (s-1)!! for even s <= 2Q-1 and 0 for odd s: the
+    moments of the unit Gaussian."""
+    x, w = gauss_hermite(Q)
+    for s in range(0, 2 * Q):
+        got = np.sum(w * x ** s)
+        ref = 0.0 if s % 2 else double_factorial(s - 1)
+        scale = np.sum(w * np.abs(x) ** s)
+        assert abs(got - ref) <= 1e-14 * scale * (1 + s), (s, got, ref)
+
+
+def gaussian_raw_moments(n, u, T, smax):
+    """Raw moments of n * N(u, T): m_s = u m_{s-1} + (s-1) T m_{s-2}
+    (integration by parts of the Gaussian)."""
+    m = [n, n * u]
+    for s in range(2, smax + 1):
+        m.append(u * m[s - 1] + (s - 1) * T * m[s - 2])
+    return np.array(m[: smax + 1])
+
+
+@pytest.mark.parametrize("Q", [16, 24])
+@pytest.mark.parametrize("nut", [(0.3, 0.0, 0.6), (0.05, 0.2, 0.9), (0.6, -0.15, 0.45), (1.0, 0.3, 1.4)])
+def test_equilibrium_reproduces_maxwellian_moments(Q, nut):
+    """The Hermite equilibrium E(n,u,T) has the exact Gaussian moments of
+    every order s <= Q-1."""
+    n, u, T = nut
+    p = Params(Q=Q, dx=1 / 8, dt=1e-3)
+    tb = step1d.Tables(p)
+    E = step1d.equilibrium(np.array([n]), np.array([u]), np.array([T]), tb)[:, 0]
+    ref = gaussian_raw_moments(n, u, T, Q - 1)
+    for s in range(Q):
+        got = np.sum(E * tb.v ** s)
+        scale = gaussian_raw_moments(n, abs(u), T, s)[s] + np.sum(np.abs(E) * np.abs(tb.v) ** s)
+        assert abs(got - ref[s]) <= 1e-12 * scale, (s, got, ref[s])
+
+
+def test_equilibrium_unit_temperature_is_weights():
+    """At T = 1, u = 0 the Maxwellian is the quadrature weight itself."""
+    p = Params(Q=16, dx=1 / 8, dt=1e-3)
+    tb = step1d.Tables(p)
+    E = step1d.equilibrium(np.array([0.7]), np.array([0.0]), np.array([1.0]), tb)[:, 0]
+    assert np.allclose(E, 0.7 * tb.w, rtol=1e-14, atol=0)
+
+
+@pytest.mark.parametrize("Q", [16, 24])
+def test_momentum_derivative_exact_on_polynomials(Q):
+    """For f(p) = omega(p) P(p) with deg P <= Q-2 the discrete derivative is
+    exact: (Dp f)_k = w_k (P'(p_k) - p_k P(p_k)) (the nodal representation
+    is f_k = w_k P(p_k))."""
+    x, w = gauss_hermite(Q)
+    D = momentum_derivative_matrix(x, w)
+    rng = np.random.default_rng(7)
+    for deg in (0, 1, 2, 5, Q - 2):
+        c = rng.standard_normal(deg + 1)
+        P = np.polynomial.Polynomial(c)
+        f = w * P(x)
+        ref = w * (P.deriv()(x) - x * P(x))
+        scale = np.max(np.abs(w * (np.abs(P.deriv()(x)) + np.abs(x * P(x))))) + 1e-300
+        assert np.max(np.abs(D @ f - ref)) <= 1e-12 * scale * Q, deg
+
+
+def test_momentum_derivative_moment_identities():
+    """sum Dp f = 0, sum p Dp f = -sum f, sum p^2/2 Dp f = -sum p f: the
+    force term changes neither mass nor energy except through work."""
+    x, w = gauss_hermite(16)
+    D = momentum_derivative_matrix(x, w)
+    f = np.random.default_rng(3).random(16)
+    scale = np.sum(np.abs(D) @ f) * np.max(x ** 2)
+    assert abs(np.sum(D @ f)) < 1e-15 * scale
+    assert abs(np.sum(x * (D @ f)) + np.sum(f)) < 1e-15 * scale
+    assert abs(np.sum(0.5 * x ** 2 * (D @ f)) + np.sum(x * f)) < 1e-15 * scale
+
+
+# ---------------------------------------------------------------------------
+# contact value, averaged density, force
+# ---------------------------------------------------------------------------
+
+def test_contact_value_equals_carnahan_starling_form():
+    """eq:carnstar, first form: chi = (p_hs/(n T) - 1)/(n b) with the
+    Carnahan-Starling Z; and chi(0) = 1."""
+    n = np.linspace(1e-4, 0.9, 50)
+    Z = model.compressibility_factor(n, 1.0)
+    chi_cs = (Z - 1.0) / (n * model.excluded_volume(1.0))
+    assert np.allclose(model.contact_value(n, 1.0), chi_cs, rtol=1e-12)
+    assert model.contact_value(0.0, 1.0) == 1.0
+
+
+def test_averaging_weights_sum_and_uniform():
+    """The averaged density of a uniform field is that field (weights sum
+    to one: Simpson is exact for the quadratic ball cross-section)."""
+    for dx in (1 / 8, 1 / 4, 1 / 10):
+        p = Params(Q=16, dx=dx, dt=1e-3)
+        assert abs(np.sum(model.averaging_weights(p)) - 1.0) < 1e-14
+
+
+def test_averaged_density_sinusoid_transfer():
+    """n = cos(k x): the ball average is 3 (sin ks - ks cos ks)/(ks)^3 cos(kx)
+    (closed form of the Fischer-Methfessel average), up to Simpson's
+    O(dx^4) error: small, and falling ~16x when dx halves."""
+    L = 64.0
+    for m in (1, 8, 40):
+        errs = []
+        for dx in (1 / 4, 1 / 8, 1 / 16):
+            N = int(L / dx)
+            x = np.arange(N) * dx
+            tb = step1d.Tables(Params(Q=16, dx=dx, dt=1e-3))
+            k = 2 * np.pi * m / L
+            n = np.cos(k * x)
+            ks = k * 1.0
+            ref = 3 * (np.sin(ks) - ks * np.cos(ks)) / ks ** 3 * n
+            errs.append(np.max(np.abs(step1d.averaged_density(n, tb) - ref)))
+        assert errs[0] < 0.1 * (1 / 4) ** 4 * (1 + ks ** 2), (m, errs)
+        assert errs[1] < errs[0] / 12 and errs[2] < errs[1] / 12, (m, errs)
+
+
+def test_force_uniform_and_antisymmetry():
+    """Uniform density gives zero force exactly; sum_i n_i F_i = 0 (the
+    mean field exerts no net force on a periodic system)."""
+    p = Params(Q=16, dx=1 / 8, dt=1e-3)
+    tb = step1d.Tables(p)
+    n = np.full(256, 0.37)
+    assert np.all(step1d.vlasov_force_ev1(n, tb) == 0.0)
+    n = 0.3 + 0.1 * np.random.default_rng(0).random(256)
+    assert abs(np.sum(n * step1d.vlasov_force_ev1(n, tb))) < 1e-13
+
+
+@pytest.mark.parametrize("dx", [1 / 4, 1 / 8])
+def test_force_sinusoid_against_quadrature(dx):
+    """n = cos(k x): F = -sin(k x) * 2 int_0^rc K(s) sin(k s) ds, with the
+    integral evaluated by adaptive quadrature (scipy quad) on the
+    continuous kernel of eq:F1; Simpson's error is O(dx^4)."""
+    N = int(64 / dx)
+    L = N * dx
+    x = np.arange(N) * dx
+    p = Params(Q=16, dx=dx, dt=1e-3)
+    tb = step1d.Tables(p)
+    for m in (1, 5, 20):
+        k = 2 * np.pi * m / L
+        inner = integrate.quad(lambda s: 2 * np.pi * s * np.sin(k * s), 0, 1, epsabs=1e-14, epsrel=1e-14)[0]
+        outer = integrate.quad(lambda s: 2 * np.pi * s ** -5 * np.sin(k * s), 1, 5, epsabs=1e-14, epsrel=1e-14)[0]
+        ref = -np.sin(k * x) * 2 * (inner + outer)
+        got = step1d.vlasov_force_ev1(np.cos(k * x), tb)
+        assert np.max(np.abs(got - ref)) < 0.5 * dx ** 4 * (1 + k ** 4) * 10, m
+
+
+def test_attraction_parameter_limits():
+    """a of eq:F2 is the first moment of the kernel: the Simpson sum tends
+    to (2 pi/3)(2 - (sigma/rc)^3) (truncated kernel) and, as rc grows, to
+    eq:F2's a = (2 pi sigma^3/3) phi gamma/(gamma-3) = 4 pi/3 at gamma = 6."""
+    assert abs(model.attraction_parameter() - 4 * np.pi / 3) < 1e-15
+    a_trunc = 2 * np.pi / 3 * (2 - 1 / 125)
+    errs = []
+    for dx in (1 / 4, 1 / 8, 1 / 16):
+        errs.append(abs(model.attraction_parameter_discrete(Params(Q=16, dx=dx, dt=1e-3)) - a_trunc))
+    assert errs[0] < 2e-2 and errs[1] < errs[0] / 10 and errs[2] < errs[1] / 10
+    big = model.attraction_parameter_discrete(Params(Q=16, dx=1 / 16, dt=1e-3, r_cut=200.0))
+    assert abs(big - 4 * np.pi / 3) < 1e-4
+
+
+# ---------------------------------------------------------------------------
+# transport
+# ---------------------------------------------------------------------------
+
+def test_prandtl_consistent_with_viscosity_and_conductivity():
+    """eq:prandtl equals c_P mu_k / lambda_k with the kinetic parts
+    mu_k = mu/(1 + 2/5 y), lambda_k = lambda/(1 + 3/5 y), c_P = 5/2, using the
+    separately printed Enskog mu and lambda (eq:viscosity)."""
+    rng = np.random.default_rng(5)
+    for _ in range(50):
+        n = rng.uniform(1e-3, 0.8)
+        T = rng.uniform(0.3, 1.5)
+        chi = model.contact_value(n, 1.0)
+        y = model.excluded_volume(1.0) * n * chi
+        mu = model.viscosity(n, T, chi, 1.0)
+        lam = model.conductivity(n, T, chi, 1.0)
+        ref = 2.5 * (mu / (1 + 0.4 * y)) / (lam / (1 + 0.6 * y))
+        assert abs(model.prandtl(n, chi, 1.0) - ref) < 1e-13
+
+
+def test_dilute_limits_of_transport():
+    """n -> 0: chi -> 1, Pr -> 2/3 (hard-sphere Eucken value) and
+    nu -> n T / mu_HS with the Chapman-Enskog hard-sphere viscosity
+    mu_HS = 5 sqrt(pi m k T) / (16 pi sigma^2)."""
+    n, T = 1e-9, 0.8
+    chi = model.contact_value(n, 1.0)
+    assert abs(model.prandtl(n, chi, 1.0) - 2 / 3) < 1e-8
+    mu_hs = 5 * math.sqrt(math.pi * T) / (16 * math.pi)
+    assert abs(model.collision_rate(n, T, chi, 1.0) / (n * T / mu_hs) - 1) < 1e-8
+
+
+# ---------------------------------------------------------------------------
+# Shakhov and J1: reduction over (p_y, p_z) checked against the 3D formulas
+# ---------------------------------------------------------------------------
+
+class _Nodes:
+    def __init__(self, v, sigma=1.0):
+        self.v = v
+        self.p = Params(Q=16, dx=1 / 8, dt=1e-3, sigma=sigma)
+
+
+def _perp_quadrature(T):
+    y, wy = gauss_hermite(12)
+    Y, Z = np.meshgrid(y, y, indexing="ij")
+    W = np.outer(wy, wy)
+    return np.sqrt(T) * Y.ravel(), np.sqrt(T) * Z.ravel(), W.ravel()
+
+
+def _gauss(x, T):
+    return np.exp(-x ** 2 / (2 * T)) / np.sqrt(2 * np.pi * T)
+
+
+def test_shakhov_reduction_matches_3d_formula():
+    """Integrate the 3D Shakhov f^S of the paper over (p_y, p_z) with a
+    tensor Gauss-Hermite rule (exact for these polynomial x Gaussian
+    integrands) and compare with the reduced F^S, G^S of the oracle."""
+    n, u, T, q, Pr = 0.4, 0.13, 0.7, 0.021, 0.8
+    px = np.linspace(-4, 4, 17)
+    xi_x = px - u
+    py, pz, W = _perp_quadrature(T)
+    FS3 = np.zeros_like(px)
+    GS3 = np.zeros_like(px)
+    for i, xx in enumerate(xi_x):
+        xi2 = xx ** 2 + py ** 2 + pz ** 2
+        corr = 1 + (1 - Pr) / (n * T * T) * (xi2 / (5 * T) - 1) * xx * q
+        FS3[i] = n * _gauss(xx, T) * np.sum(W * corr)
+        GS3[i] = n * _gauss(xx, T) * np.sum(W * 0.5 * (py ** 2 + pz ** 2) * corr)
+    E = (n * _gauss(xi_x, T))[:, None]
+    a = lambda v: np.array([v])
+    FS, GS = step1d.shakhov(E, a(u), a(T), a(n), a(q), a(Pr), _Nodes(px))
+    assert np.allclose(FS[:, 0], FS3, rtol=1e-13, atol=1e-16)
+    assert np.allclose(GS[:, 0], GS3, rtol=1e-13, atol=1e-16)
+
+
+def test_j1_reduction_matches_3d_formula():
+    """eq:J1 with gradients along x only, integrated over (p_y, p_z) by a
+    tensor Gauss-Hermite rule, against the reduced J1F, J1G."""
+    n, u, T, chi, A, B, U = 0.35, -0.08, 0.62, 1.9, 0.3, -0.2, 0.05
+    b = model.excluded_volume(1.0)
+    px = np.linspace(-4, 4, 17)
+    xi_x = px - u
+    py, pz, W = _perp_quadrature(T)
+    J1F3 = np.zeros_like(px)
+    J1G3 = np.zeros_like(px)
+    for i, xx in enumerate(xi_x):
+        zeta2 = (xx ** 2 + py ** 2 + pz ** 2) / (2 * T)
+        zx2 = xx ** 2 / (2 * T)
+        brace = xx * (A + 0.6 * (zeta2 - 2.5) * B) + 0.4 * (2 * zx2 * U + (zeta2 - 2.5) * U)
+        J1F3[i] = -b * n * chi * n * _gauss(xx, T) * np.sum(W * brace)
+        J1G3[i] = -b * n * chi * n * _gauss(xx, T) * np.sum(W * 0.5 * (py ** 2 + pz ** 2) * brace)
+    E = (n * _gauss(xi_x, T))[:, None]
+    a = lambda v: np.array([v])
+    J1F, J1G = step1d.j1_terms(E, a(u), a(T), a(n), a(chi), a(A), a(B), a(U), _Nodes(px))
+    assert np.allclose(J1F[:, 0], J1F3, rtol=1e-12, atol=1e-15)
+    assert np.allclose(J1G[:, 0], J1G3, rtol=1e-12, atol=1e-15)
+
+
+def _random_state(N=128, Q=16, dx=1 / 8, seed=11, amp=0.05, **kw):
+    dt = 0.2 * dx / gauss_hermite(Q)[0][-1]
+    p = Params(Q=Q, dx=dx, dt=dt, **kw)
+    tb = step1d.Tables(p)
+    rng = np.random.default_rng(seed)
+    x = np.arange(N) * dx
+    L = N * dx
+    n = 0.3 * (1 + amp * np.sin(2 * np.pi * x / L) + 0.01 * rng.standard_normal(N))
+    u = 0.05 * np.cos(2 * np.pi * 2 * x / L)
+    T = 0.6 * (1 + 0.05 * np.sin(2 * np.pi * 3 * x / L))
+    F, G = step1d.initial_state(n, u, T, tb)
+    # non-equilibrium part with a heat flux
+    F = F * (1 + 0.02 * rng.standard_normal(F.shape) * tb.w[:, None] / tb.w.max())
+    return F, G, tb
+
+
+def test_shakhov_discrete_moments():
+    """On the quadrature, F^S keeps n, n u, the energy and has heat flux
+    (1 - Pr) q."""
+    F, G, tb = _random_state()
+    m = step1d.node_fields(F, G, tb)
+    E = step1d.equilibrium(m["n"], m["u"], m["T"], tb)
+    FS, GS = step1d.shakhov(E, m["u"], m["T"], m["n"], m["q"], m["Pr"], tb)
+    n2, u2, T2, q2 = step1d.moments(FS, GS, tb)
+    assert np.allclose(n2, m["n"], rtol=1e-13)
+    assert np.allclose(u2, m["u"], rtol=0, atol=1e-13)
+    assert np.allclose(T2, m["T"], rtol=1e-13)
+    assert np.allclose(q2, (1 - m["Pr"]) * m["q"], rtol=0, atol=1e-13)
+
+
+def test_j1_discrete_moments():
+    """J1 adds no mass; its momentum is -b dX/dx and its energy
+    -b (X du/dx + u dX/dx), X = n^2 chi T (the collisional transfer)."""
+    F, G, tb = _random_state()
+    m = step1d.node_fields(F, G, tb)
+    E = step1d.equilibrium(m["n"], m["u"], m["T"], tb)
+    J1F, J1G = step1d.j1_terms(E, m["u"], m["T"], m["n"], m["chi"], m["A"], m["B"], m["U"], tb)
+    b = model.excluded_volume(1.0)
+    DX = m["A"] * m["X"]
+    v = tb.v[:, None]
+    assert np.max(np.abs(J1F.sum(0))) < 1e-14
+    assert np.allclose((v * J1F).sum(0), -b * DX, rtol=0, atol=1e-13)
+    assert np.allclose((0.5 * v ** 2 * J1F + J1G).sum(0), -b * (m["X"] * m["U"] + m["u"] * DX), rtol=0, atol=1e-13)
+
+
+# ---------------------------------------------------------------------------
+# WENO-5 against the polynomial definition (Jiang & Shu)
+# ---------------------------------------------------------------------------
+
+def _cell_poly(vals, centres):
+    """Quadratic whose averages over unit cells centred at `centres` equal
+    `vals` (the reconstruction polynomial of a 3-cell stencil)."""
+    M = np.zeros((3, 3))
+    for r, c in enumerate(centres):
+        for d in range(3):
+            # average of x^d over [c-1/2, c+1/2]
+            M[r, d] = ((c + 0.5) ** (d + 1) - (c - 0.5) ** (d + 1)) / (d + 1)
+    return np.polynomial.Polynomial(np.linalg.solve(M, vals))
+
+
+def test_weno_against_polynomial_definition():
+    """q_r = p_r(1/2), beta_r = int_{-1/2}^{1/2} (p_r')^2 + (p_r'')^2 dx on
+    unit cells, alpha_r = d_r/(eps + beta_r)^2, d = (1/10, 6/10, 3/10)."""
+    rng = np.random.default_rng(2)
+    for _ in range(40):
+        f = rng.standard_normal(5) * 10 ** rng.uniform(-3, 0)
+        eps = 1e-6
+        qs, bs = [], []
+        for r, cells in enumerate(([-2, -1, 0], [-1, 0, 1], [0, 1, 2])):
+            P = _cell_poly(f[np.array(cells) + 2], cells)
+            qs.append(P(0.5))
+            d1, d2 = P.deriv(), P.deriv(2)
+            I = (d1 ** 2 + d2 ** 2).integ()
+            bs.append(I(0.5) - I(-0.5))
+        al = np.array([0.1, 0.6, 0.3]) / (eps + np.array(bs)) ** 2
+        ref = np.sum(al * np.array(qs)) / np.sum(al)
+        got = step1d.weno5_reconstruct(*f, eps)
+        assert abs(got - ref) <= 1e-12 * np.max(np.abs(f)), (got, ref)
+
+
+def test_weno_linear_limit_is_fifth_order_upwind():
+    """For data far below eps the weights are the linear ones and the face
+    value is the 5-cell upwind reconstruction
+    (2 f_-2 - 13 f_-1 + 47 f_0 + 27 f_1 - 3 f_2)/60."""
+    f = 1e-12 * np.random.default_rng(4).standard_normal(5)
+    ref = (2 * f[0] - 13 * f[1] + 47 * f[2] + 27 * f[3] - 3 * f[4]) / 60
+    assert abs(step1d.weno5_reconstruct(*f, 1e-6) - ref) < 1e-14 * 1e-12
+
+
+def test_weno_advection_convergence():
+    """Free streaming operator on smooth data converges to -p f' at
+    close to fifth order."""
+    errs = []
+    for N in (32, 64, 128):
+        dx = 2 * np.pi / N
+        p = Params(Q=16, dx=1 / 8, dt=1e-3)
+        tb = step1d.Tables(p)
+        tb.p = Params(Q=16, dx=1 / 8, dt=1e-3)
+        tb.p.dx = dx
+        x = np.arange(N) * dx
+        f = np.tile(1.0 + 0.3 * np.sin(x) + 0.1 * np.cos(2 * x), (16, 1))
+        ref = -tb.v[:, None] * (0.3 * np.cos(x) - 0.2 * np.sin(2 * x))[None, :]
+        errs.append(np.max(np.abs(step1d.weno5_advection(f, tb) - ref) / np.abs(tb.v)[:, None]))
+    order = np.log2(errs[1] / errs[2])
+    assert order > 4.0, errs
+
+
+# ---------------------------------------------------------------------------
+# equation of state
+# ---------------------------------------------------------------------------
+
+def test_critical_temperature_matches_paper():
+    """Sec. III A prints T_c ~= 0.754632 for the EV fluid (eq:EOSS with
+    eq:F2's a = 4 pi/3 at gamma = 6)."""
+    n_c, T_c, P_c = model.critical_point(model.attraction_parameter())
+    assert abs(T_c - 0.754632) < 5e-6
+    h = 1e-4
+    P = lambda n: model.pressure(n, T_c, model.attraction_parameter())
+    assert abs((P(n_c + h) - P(n_c - h)) / (2 * h)) < 1e-7
+    assert abs((P(n_c + h) - 2 * P(n_c) + P(n_c - h)) / h ** 2) < 1e-5
+
+
+def test_chemical_potential_gibbs_duhem():
+    """d mu/dn = (1/n) dP/dn at fixed T (finite differences)."""
+    a = model.attraction_parameter()
+    for n in (0.02, 0.2, 0.6):
+        h = 1e-6 * n
+        dmu = (model.chemical_potential(n + h, 0.6, a) - model.chemical_potential(n - h, 0.6, a)) / (2 * h)
+        dP = (model.pressure(n + h, 0.6, a) - model.pressure(n - h, 0.6, a)) / (2 * h)
+        assert abs(dmu - dP / n) < 1e-6 * abs(dP / n)
+
+
+@pytest.mark.parametrize("T", [0.55, 0.6, 0.7, 0.74])
+def test_maxwell_equal_area(T):
+    """Coexistence densities satisfy the equal-area rule
+    int_{v_l}^{v_v} P dv = P_sat (v_v - v_l), v = 1/n (adaptive quadrature),
+    and lie outside the spinodal."""
+    a = model.attraction_parameter()
+    nv, nl = model.maxwell_construction(T, a)
+    Ps = model.pressure(nv, T, a)
+    assert abs(model.pressure(nl, T, a) - Ps) < 1e-13
+    area = integrate.quad(lambda v: model.pressure(1 / v, T, a), 1 / nl, 1 / nv, epsrel=1e-13, limit=200)[0]
+    assert abs(area - Ps * (1 / nv - 1 / nl)) < 1e-9 * abs(Ps) * (1 / nv)
+    sv, sl = model.spinodal(T, a)
+    assert nv < sv < sl < nl
+
+
+# ---------------------------------------------------------------------------
+# whole step
+# ---------------------------------------------------------------------------
+
+def test_uniform_maxwellian_is_stationary():
+    """A uniform Maxwellian at rest stays stationary (full model)."""
+    p = Params(Q=16, dx=1 / 8, dt=0.2 / 8 / 6.6308782)
+    tb = step1d.Tables(p)
+    F, G = step1d.initial_state(np.full(64, 0.3), 0.0, 0.6, tb)
+    F1, G1 = step1d.run(F, G, tb, 100)
+    assert np.max(np.abs(F1 - F)) <= 1e-14 * np.max(F)
+    assert np.max(np.abs(G1 - G)) <= 1e-14 * np.max(G)
+
+
+def test_initial_state_moments():
+    F, G, tb = _random_state(amp=0.0)
+    p = tb.p
+    tb2 = step1d.Tables(p)
+    n = np.linspace(0.1, 0.6, 7)
+    u = np.linspace(-0.2, 0.2, 7)
+    T = np.linspace(0.5, 0.9, 7)
+    F, G = step1d.initial_state(n, u, T, tb2)
+    n2, u2, T2, q2 = step1d.moments(F, G, tb2)
+    assert np.allclose(n2, n, rtol=1e-14) and np.allclose(u2, u, atol=1e-14)
+    assert np.allclose(T2, T, rtol=1e-13) and np.max(np.abs(q2)) < 1e-14
+
+
+def test_conservation_full_model():
+    """Periodic system: mass and momentum conserved to round-off; the
+    energy changes exactly by the work of the mean-field force,
+    dE = dt (1/6 W(f^n) + 1/6 W(f1) + 2/3 W(f2)), W = sum_i n u F."""
+    F, G, tb = _random_state()
+    v = tb.v[:, None]
+    for _ in range(5):
+        mass0 = F.sum()
+        mom_scale = np.sum(np.abs(v) * F)
+        mom0 = (v * F).sum()
+        en0 = (0.5 * v ** 2 * F + G).sum()
+        work = []
+        Fs, Gs = F, G
+        for a, b in step1d.RK3_COEFFS:
+            m = step1d.node_fields(Fs, Gs, tb)
+            work.append(np.sum(m["n"] * m["u"] * m["Fx"]))
+            LF, LG = step1d.rhs(Fs, Gs, tb)
+            Fs, Gs = a * F + b * (Fs + tb.p.dt * LF), a * G + b * (Gs + tb.p.dt * LG)
+        F1, G1 = step1d.rk3_step(F, G, tb)
+        assert np.array_equal(F1, Fs)
+        assert abs(F1.sum() - mass0) < 1e-13 * mass0
+        assert abs((v * F1).sum() - mom0) < 1e-13 * mom_scale
+        en1 = (0.5 * v ** 2 * F1 + G1).sum()
+        budget = tb.p.dt * (work[0] / 6 + work[1] / 6 + 2 * work[2] / 3)
+        assert abs(en1 - en0 - budget) < 1e-13 * en0
+        F, G = F1, G1
+
+
+def test_energy_conserved_without_attraction():
+    F, G, tb = _random_state(phi=0.0)
+    v = tb.v[:, None]
+    en0 = (0.5 * v ** 2 * F + G).sum()
+    F1, G1 = step1d.run(F, G, tb, 5)
+    assert abs((0.5 * v ** 2 * F1 + G1).sum() - en0) < 1e-13 * en0
+
+
+def test_homogeneous_relaxation_closed_form():
+    """Uniform non-equilibrium state: the stress P_xx - n T decays by
+    R(-nu dt) and the heat flux by R(-Pr nu dt) per step,
+    R(z) = 1 + z + z^2/2 + z^3/6 (the TVD-RK3 stability polynomial)."""
+    N, Q = 16, 16
+    p = Params(Q=Q, dx=1 / 8, dt=0.05)
+    tb = step1d.Tables(p)
+    n0, T0 = 0.45, 0.7
+    F, G = step1d.initial_state(np.full(N, n0), 0.0, T0, tb)
+    He = hermite_table(tb.v, 3)
+    eps = 1e-3
+    F = F + eps * (tb.w * He[2])[:, None] + 0.5 * eps * (tb.w * He[3])[:, None]
+    G = G - eps * tb.w[:, None]
+    m = step1d.node_fields(F, G, tb)
+    nu, Pr = m["nu"][0], m["Pr"][0]
+    R = lambda z: 1 + z + z * z / 2 + z ** 3 / 6
+    v = tb.v[:, None]
+    s0 = (v ** 2 * F).sum(0)[0] - n0 * T0
+    q0 = m["q"][0]
+    F1, G1 = step1d.rk3_step(F, G, tb)
+    n1, u1, T1, q1 = step1d.moments(F1, G1, tb)
+    s1 = (v ** 2 * F1).sum(0)[0] - n1[0] * T1[0]
+    assert abs(s1 / s0 - R(-nu * p.dt)) < 1e-11
+    assert abs(q1[0] / q0 - R(-Pr * nu * p.dt)) < 1e-11
+
+
+def test_uniform_external_force():
+    """Force term alone on a uniform Maxwellian with a uniform external
+    acceleration g: u grows as g t, T stays fixed (up to round-off)."""
+    p = Params(Q=16, dx=1 / 8, dt=0.01, term_mask=TERM_FORCE, force_model=FORCE_NONE, g_ext=0.2)
+    tb = step1d.Tables(p)
+    F, G = step1d.initial_state(np.full(8, 0.3), 0.0, 0.6, tb)
+    F1, G1 = step1d.run(F, G, tb, 50)
+    n, u, T, q = step1d.moments(F1, G1, tb)
+    assert np.allclose(u, 0.2 * 50 * 0.01, rtol=1e-12)
+    assert np.allclose(T, 0.6, rtol=1e-12)
+
+
+def test_free_streaming_translation():
+    """Advection alone: each velocity row is translated by p_k t; error
+    against the exact translation of a smooth profile falls fast with dx."""
+    errs = []
+    for N in (64, 128):
+        L = 16.0
+        dx = L / N
+        p = Params(Q=8, dx=1 / 8, dt=1e-3, term_mask=TERM_ADV)
+        tb = step1d.Tables(p)
+        tb.p.dx = dx
+        vmax = tb.v[-1]
+        steps = N // 4
+        tb.p.dt = 0.5 / vmax / steps   # fixed end time
+        x = np.arange(N) * dx
+        prof = lambda y: 1 + 0.2 * np.sin(2 * np.pi * y / L)
+        F = np.array([prof(x) for _ in tb.v]) * tb.w[:, None]
+        G = F.copy()
+        F1, _ = step1d.run(F, G, tb, steps)
+        t = steps * tb.p.dt
+        ref = np.array([prof(x - pk * t) for pk in tb.v]) * tb.w[:, None]
+        errs.append(np.max(np.abs(F1 - ref) / tb.w[:, None]))
+    assert errs[1] < errs[0] / 12, errs
+
+
+@pytest.mark.parametrize("n0,T", [(0.05, 0.65), (0.3, 0.65), (0.6, 0.5)])
+def test_bulk_pressure_is_equation_of_state(n0, T):
+    """Long-wave isothermal density wave at rest: the momentum right-hand
+    side sum_k p_k L^F_k tends to -dP/dx with P the generalized van der
+    Waals pressure of eq:EOSS (Carnahan-Starling + mean field with the
+    discrete kernel's a).  The kinetic, collisional and mean-field parts
+    can cancel, so the tolerance is relative to their magnitudes; the
+    neglected terms are O((k sigma)^2) ~ 1e-3."""
+    N, dx = 1024, 1 / 8
+    p = Params(Q=16, dx=dx, dt=1e-3)
+    tb = step1d.Tables(p)
+    x = np.arange(N) * dx
+    k = 2 * np.pi / (N * dx)
+    n = n0 * (1 + 0.05 * np.cos(k * x))
+    F, G = step1d.initial_state(n, 0.0, T, tb)
+    LF, LG = step1d.rhs(F, G, tb)
+    mom = (tb.v[:, None] * LF).sum(0)
+    a = model.attraction_parameter_discrete(p)
+    dn = -n0 * 0.05 * k * np.sin(k * x)
+    h = 1e-7
+    d = lambda f: (f(n + h) - f(n - h)) / (2 * h)
+    dPdn = d(lambda m: model.pressure(m, T, a))
+    parts = np.abs(d(lambda m: m * T)) + np.abs(d(lambda m: m * T * (model.compressibility_factor(m, 1.0) - 1))) \
+        + np.abs(d(lambda m: a * m ** 2))
+    ref = -dPdn * dn
+    assert np.max(np.abs(mom - ref)) < 1e-3 * np.max(parts * np.abs(dn))
+
+
+def test_complex_step_matches_finite_difference():
+    """The oracle runs in complex128: d/dphi of a scalar of the state by
+    complex step agrees with a central finite difference."""
+    N, Q = 32, 8
+    def J(phi):
+        p = Params(Q=Q, dx=1 / 8, dt=0.02, phi=phi)
+        tb = step1d.Tables(p)
+        x = np.arange(N) / 8
+        n = 0.3 * (1 + 0.1 * np.sin(2 * np.pi * x / 4))
+        F, G = step1d.initial_state(n.astype(np.result_type(phi, float)), 0.0, 0.6, tb)
+        F, G = step1d.run(F, G, tb, 3)
+        return np.sum(F[:, :8] ** 2)
+    h = 1e-30
+    cs = J(1.0 + 1j * h).imag / h
+    fd = (J(1.0 + 1e-5) - J(1.0 - 1e-5)) / 2e-5
+    assert abs(cs - fd) < 1e-10 * max(1.0, abs(J(1.0)))
+    assert abs(cs) > 1e-6
+
+
+def test_collisional_transfer_uses_ball_averaged_density():
+    """Short density wave (wavelength ~4 sigma): the J1 momentum source is
+    -b d/dx (n^2 chi(nbar) T) with nbar the ball average of Sec. II A,
+    here from its closed-form transfer function, not the local n."""
+    N, dx = 512, 1 / 8
+    L = N * dx
+    p = Params(Q=16, dx=dx, dt=1e-3, term_mask=TERM_J1)
+    tb = step1d.Tables(p)
+    x = np.arange(N) * dx
+    k = 2 * np.pi * 16 / L
+    n0, eps, T = 0.35, 0.05, 0.7
+    n = n0 * (1 + eps * np.cos(k * x))
+    F, G = step1d.initial_state(n, 0.0, T, tb)
+    LF, _ = step1d.rhs(F, G, tb)
+    mom = (tb.v[:, None] * LF).sum(0)
+    tr = 3 * (np.sin(k) - k * np.cos(k)) / k ** 3
+    b = model.excluded_volume(1.0)
+
+    def X(y):
+        ny = n0 * (1 + eps * np.cos(k * y))
+        nb = n0 * (1 + eps * tr * np.cos(k * y))
+        return ny ** 2 * model.contact_value(nb, 1.0) * T
+
+    h = 1e-5
+    ref = -b * (X(x + h) - X(x - h)) / (2 * h)
+    assert np.max(np.abs(mom - ref)) < 2e-3 * np.max(np.abs(ref))
+    # the local-density reading differs at the percent level
+    Xloc = lambda y: (n0 * (1 + eps * np.cos(k * y))) ** 2 * model.contact_value(n0 * (1 + eps * np.cos(k * y)), 1.0) * T
+    alt = -b * (Xloc(x + h) - Xloc(x - h)) / (2 * h)
+    assert np.max(np.abs(alt - ref)) > 1e-2 * np.max(np.abs(ref))
+
+
+def test_ev2_force_on_sinusoid():
+    """eq:F2 on n = cos(k x): F2 = -2 a k sin(kx) + kappa k^3 sin(kx) with
+    a = 4 pi/3, kappa = 4 pi/5 at gamma = 6 (up to the O(dx^2) error of the
+    5-point third derivative)."""
+    N, dx = 512, 1 / 8
+    p = Params(Q=16, dx=dx, dt=1e-3, force_model=model.FORCE_EV2)
+    tb = step1d.Tables(p)
+    x = np.arange(N) * dx
+    k = 2 * np.pi * 8 / (N * dx)
+    got = step1d.vlasov_force(np.cos(k * x), tb)
+    ref = (-2 * (4 * np.pi / 3) * k + (4 * np.pi / 5) * k ** 3) * np.sin(k * x)
+    assert np.max(np.abs(got - ref)) < 1e-3 * np.max(np.abs(ref))
