@@ -1,0 +1,160 @@
+/*
+ * evlb.h -- C ABI of the MI355X (gfx950) Enskog-Vlasov finite-difference
+ * lattice Boltzmann (EV-FDLB) time step.
+ *
+ * Method: Busuioc & Sofonea, "Thermal Enskog-Vlasov Lattice Boltzmann model
+ * with phase separation", arXiv:2503.15187.  The library advances the
+ * reduced 1D distributions F(x, p), G(x, p) of a fluid homogeneous in y and
+ * z (Sec. III) under the simplified Enskog-Vlasov equation (eq:enskog_approx
+ * with the EV1 force eq:F1, or the EV2 force eq:F2), discretised on an
+ * off-lattice full-range Gauss-Hermite velocity set, with WENO-5 advection,
+ * 4th-order central gradients and TVD Runge-Kutta 3 in time (Sec. III,
+ * numerical schemes paragraph).
+ *
+ * Conventions shared by every call
+ *  - All floating point is IEEE double (FP64).
+ *  - Pointers named d_* are DEVICE pointers (HIP global memory on the device
+ *    current at evlb_init).  Pointers named h_* or documented as host are
+ *    host memory.  The library allocates no device memory: the caller owns
+ *    the state, the outputs and the workspace, and must keep the workspace
+ *    alive and untouched while the context exists.
+ *  - hip_stream is a hipStream_t passed as void* (NULL = the null stream).
+ *    Device work is enqueued asynchronously on it; results are ready when the
+ *    stream is synchronised.
+ *  - Distribution layout: d_f[2][q][n_tot], structure of arrays, node index
+ *    fastest.  Plane 0 holds F_k, plane 1 holds G_k; the velocity rows k are
+ *    the Gauss-Hermite nodes in ascending order.  System s occupies nodes
+ *    [off_s, off_s + nx[s]) with off_s = nx[0] + ... + nx[s-1]; each system
+ *    is periodic on its own.
+ *  - Node-field layout: d_n, d_u, d_T, d_q are [n_tot].
+ *  - Return value: EVLB_OK or a negative error code.  Argument errors are
+ *    detected on the host before any device work is enqueued and leave all
+ *    buffers untouched.  Device-detected errors (a non-positive or
+ *    non-finite density or temperature produced by a step) are latched in
+ *    the workspace and reported by evlb_status.
+ *  - A context is bound to one device and is not thread-safe; calls that
+ *    share a workspace must be ordered on one stream.
+ */
+#ifndef EVLB_H
+#define EVLB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define EVLB_ABI_VERSION 1
+
+enum {
+  EVLB_OK = 0,
+  EVLB_EINVAL = -1,       /* bad argument or parameter                      */
+  EVLB_ECFL = -2,         /* dt * max|p_k| / dx above the stability limit   */
+  EVLB_EWORKSPACE = -3,   /* workspace missing, too small or misaligned     */
+  EVLB_EHIP = -4,         /* a HIP runtime call failed                      */
+  EVLB_ENONFINITE = -5,   /* a step produced n <= 0, T <= 0 or NaN          */
+  EVLB_EUNSUPPORTED = -6  /* valid but not built (e.g. quadrature order)    */
+};
+
+/* Self-consistent force model (Sec. II C, eq:ev_12). */
+enum { EVLB_FORCE_EV1 = 0, EVLB_FORCE_EV2 = 1, EVLB_FORCE_NONE = 2 };
+
+/* Right-hand-side terms; production runs use EVLB_TERM_ALL.  The others
+ * exist to test one term at a time. */
+enum {
+  EVLB_TERM_ADV = 1,    /* -p dF/dx (WENO-5)                                */
+  EVLB_TERM_FORCE = 2,  /* -F[n] dF/dp                                      */
+  EVLB_TERM_J0 = 4,     /* -(chi/tau)(f - f^S), Shakhov                     */
+  EVLB_TERM_J1 = 8,     /* J1(f_MB, f_MB), eq:J1                            */
+  EVLB_TERM_ALL = 15
+};
+
+/* Launch strategy of evlb_step. */
+enum {
+  EVLB_EXEC_AUTO = 0,       /* persistent for small grids, else per stage   */
+  EVLB_EXEC_PER_STAGE = 1,  /* one fused kernel per Runge-Kutta stage       */
+  EVLB_EXEC_PERSISTENT = 2  /* one cooperative launch for all nsteps        */
+};
+
+typedef struct {
+  int32_t abi_version;   /* must be EVLB_ABI_VERSION                         */
+  int32_t dim;           /* 1                                                */
+  int32_t n_sys;         /* >= 1 independent periodic systems                */
+  const int32_t* nx;     /* host [n_sys]: nodes per system, each >= 8        */
+  int32_t q;             /* Gauss-Hermite order: 8, 16 or 24                 */
+  double dx;             /* grid spacing; sigma/dx and r_cut/dx even ints    */
+  double dt;             /* time step                                        */
+  double sigma;          /* hard-sphere diameter (eq:sutherland)             */
+  double phi_sigma;      /* well depth of the attractive tail                */
+  double gamma;          /* tail exponent (> 3; > 5 for EV2)                 */
+  double r_cut;          /* truncation radius of the EV1 kernel (absolute)   */
+  int32_t force_model;   /* EVLB_FORCE_*                                     */
+  int32_t term_mask;     /* EVLB_TERM_* bits                                 */
+  double weno_eps;       /* WENO-5 epsilon, 1e-6                             */
+  double g_ext;          /* uniform external acceleration (tests), usually 0 */
+  int32_t exec_mode;     /* EVLB_EXEC_*                                      */
+} evlb_params;
+
+typedef struct evlb_ctx evlb_ctx; /* opaque, host memory */
+
+/* Host only.  Checks a parameter set; EVLB_OK if evlb_init would accept it
+ * (apart from the workspace).  No device call. */
+int evlb_validate(const evlb_params* params);
+
+/* Host only.  Bytes of device workspace evlb_init needs for these
+ * parameters, or 0 if they are invalid.  The workspace must be 256-byte
+ * aligned. */
+size_t evlb_workspace_bytes(const evlb_params* params);
+
+/* Builds the quadrature (roots of He_q, normalised Christoffel weights),
+ * the Hermite equilibrium and momentum-derivative tables, the Simpson
+ * weights of the averaged density (Sec. II A) and of the force (eq:F1),
+ * copies them into d_workspace on hip_stream and returns a context in
+ * *out.  d_workspace: device, >= evlb_workspace_bytes(params) bytes,
+ * owned by the caller.  The context keeps a copy of params (and of nx). */
+int evlb_init(const evlb_params* params, void* d_workspace, size_t ws_bytes,
+              void* hip_stream, evlb_ctx** out);
+
+/* Writes the reduced Maxwellian of the given node fields into d_f:
+ * F_k = E_k(n, u, T) (Hermite expansion to order q-1), G_k = T E_k.
+ * d_n, d_u, d_T: device [n_tot], read only.  d_f: device [2][q][n_tot]. */
+int evlb_set_equilibrium(evlb_ctx* ctx, const double* d_n, const double* d_u,
+                         const double* d_T, double* d_f, void* hip_stream);
+
+/* Advances d_f (device [2][q][n_tot], in/out) by nsteps >= 0 TVD-RK3 steps
+ * of size dt.  Every stage re-evaluates the moments, the averaged density
+ * and contact value (eq:carnstar), the Vlasov force (eq:F1 / eq:F2), the
+ * transport coefficients (eq:viscosity, eq:tau, eq:prandtl), the Hermite
+ * equilibrium, the Shakhov term, J1 (eq:J1), the momentum derivative and
+ * the WENO-5 flux.  Uses the workspace for stage buffers. */
+int evlb_step(evlb_ctx* ctx, double* d_f, int32_t nsteps, void* hip_stream);
+
+/* Right-hand side L(f) of the semi-discrete system at one state:
+ * d_L[2][q][n_tot] = dF/dt, dG/dt (device).  d_f is read only. */
+int evlb_rhs(evlb_ctx* ctx, const double* d_f, double* d_L, void* hip_stream);
+
+/* Moments of d_f (Sec. II B): n = sum F, n u = sum p F,
+ * 3/2 n T = sum (xi^2/2 F + G), q = sum xi (xi^2/2 F + G), xi = p - u.
+ * Outputs device [n_tot]; d_q may be NULL. */
+int evlb_moments(evlb_ctx* ctx, const double* d_f, double* d_n, double* d_u,
+                 double* d_T, double* d_q, void* hip_stream);
+
+/* Synchronises hip_stream and reports the latched device status:
+ * EVLB_OK or EVLB_ENONFINITE.  Clears the latch when clear != 0. */
+int evlb_status(evlb_ctx* ctx, void* hip_stream, int32_t clear);
+
+/* Node count n_tot and quadrature nodes (host copy, length q) of a context. */
+int evlb_info(const evlb_ctx* ctx, int64_t* n_tot, double* h_velocities);
+
+/* Releases the host context (not the caller's device memory). */
+void evlb_destroy(evlb_ctx* ctx);
+
+/* Static description of an error code. */
+const char* evlb_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EVLB_H */

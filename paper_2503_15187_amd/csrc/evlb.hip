@@ -1,0 +1,873 @@
+// EV-FDLB time step for MI355X (gfx950): fused HIP kernels and the C ABI
+// declared in include/evlb.h.
+//
+// One TVD-RK3 stage is ONE kernel.  A workgroup owns a tile of W = 64
+// consecutive nodes of one periodic system and all q velocities:
+//   1. load     F, G rows of the tile plus a 3-node halo (WENO-5) into LDS;
+//               the density window (force / averaged density halo) and
+//               u, T (gradient halo) from the moments of the previous stage.
+//   2. fields   averaged density and contact value (eq:carnstar, Sec. II A)
+//               on the tile +-2; WENO-5 face values of every row.
+//   3. fields   Vlasov force (eq:F1 / eq:F2), transport (eq:viscosity,
+//               eq:tau, eq:prandtl), J1 gradients (eq:J1) per node.
+//   4. update   lanes = nodes, wavefront = group of velocities: Hermite
+//               equilibrium, momentum derivative, Shakhov term, J1, advection,
+//               RK3 combine; partial velocity moments of the new state.
+//   5. reduce   moments (n, u, T, q) of the new state -> global, read by the
+//               next stage.
+// Global state is structure-of-arrays [2][q][n_tot] (node fastest), so every
+// row load and store of a wavefront is one contiguous 512-byte segment.
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/evlb.h"
+#include "tables.h"
+
+namespace {
+
+constexpr int W = 64;          // nodes per tile == lanes of a wavefront
+constexpr int HF = 3;          // distribution halo of the WENO-5 faces
+constexpr int MS_MAX = 16;     // max sigma/dx
+constexpr int MF_MAX = 64;     // max r_cut/dx
+constexpr int HN_MAX = MF_MAX; // density window half width
+constexpr int NFIELD = 10;
+
+enum { NF_N, NF_U, NF_T, NF_NU, NF_S, NF_PRE, NF_A, NF_B, NF_U1, NF_FX };
+
+struct DevParams {
+  const double* vel;   // [q]
+  const double* meq;   // [q][q]
+  const double* dpm;   // [q][q]
+  const double* savg;  // [2 ms + 1]
+  const double* cfor;  // [mf]
+  const int4* tiles;   // {system offset, system nodes, tile start, 0}
+  int ntiles;
+  int ms, mf, hn;
+  long long ntot;
+  double dx, inv_dx, dt;
+  double b;        // 2 pi sigma^3 / 3
+  double eta_c;    // pi sigma^3 / 6
+  double mu0c;     // 5 / (16 sigma^2 sqrt(pi)):  mu0 = mu0c sqrt(T)
+  double weno_eps, g_ext, two_a, kappa;
+  int force_model, term_mask;
+  int* status;     // [0] non-finite latch, [1] barrier abort latch
+  unsigned* bar;   // [0] arrival count, [1] generation
+};
+
+struct StageArgs {
+  const double* f_prev;  // f^(s-1)
+  const double* f_n;     // f^n (RK3 base)
+  double* f_out;         // f^(s), or L(f) in rhs mode
+  const double* mom_in;  // [4][ntot] n, u, T, q of f_prev
+  double* mom_out;       // [4][ntot] of f_out
+  double alpha, beta;    // f_out = alpha f_n + beta (f_prev + dt L)
+  int first;             // f_n == f_prev
+  int rhs_mode;          // write L(f_prev) instead of a stage
+};
+
+__device__ __forceinline__ int wrap(int i, int n) {
+  int r = i % n;
+  return r < 0 ? r + n : r;
+}
+
+// Classical WENO-5 (Jiang & Shu) face value from the five upwind-ordered
+// values v0..v4 = f_{i-2}..f_{i+2}; alpha_r = d_r/(eps+beta_r)^2 combined
+// over a common denominator (one division).
+__device__ __forceinline__ double weno5(double v0, double v1, double v2, double v3, double v4,
+                                        double eps) {
+  const double q0 = (2.0 * v0 - 7.0 * v1 + 11.0 * v2) * (1.0 / 6.0);
+  const double q1 = (-v1 + 5.0 * v2 + 2.0 * v3) * (1.0 / 6.0);
+  const double q2 = (2.0 * v2 + 5.0 * v3 - v4) * (1.0 / 6.0);
+  const double c0 = v0 - 2.0 * v1 + v2, e0 = v0 - 4.0 * v1 + 3.0 * v2;
+  const double c1 = v1 - 2.0 * v2 + v3, e1 = v1 - v3;
+  const double c2 = v2 - 2.0 * v3 + v4, e2 = 3.0 * v2 - 4.0 * v3 + v4;
+  const double b0 = (13.0 / 12.0) * c0 * c0 + 0.25 * e0 * e0;
+  const double b1 = (13.0 / 12.0) * c1 * c1 + 0.25 * e1 * e1;
+  const double b2 = (13.0 / 12.0) * c2 * c2 + 0.25 * e2 * e2;
+  double t0 = eps + b0; t0 *= t0;
+  double t1 = eps + b1; t1 *= t1;
+  double t2 = eps + b2; t2 *= t2;
+  const double w0 = 0.1 * t1 * t2, w1 = 0.6 * t0 * t2, w2 = 0.3 * t0 * t1;
+  return (w0 * q0 + w1 * q1 + w2 * q2) / (w0 + w1 + w2);
+}
+
+template <int Q, int NW>
+struct Smem {
+  double f[2 * Q][W + 2 * HF];
+  union {
+    double flux[2 * Q][W + 1];
+    double red[NW][6][W];
+  };
+  double n[W + 2 * HN_MAX];
+  double u[W + 4], T[W + 4], chi[W + 4], X[W + 4];
+  double nf[NFIELD][W];
+};
+
+// One stage over one tile (see file header).
+template <int Q, int NW>
+__device__ void stage_tile(const DevParams& P, const StageArgs& A, int tile, Smem<Q, NW>& S) {
+  constexpr int NT = 64 * NW;
+  constexpr int VPT = Q / NW;
+  static_assert(Q % NW == 0, "velocity groups must divide q");
+  const int tid = threadIdx.x;
+  const int4 td = P.tiles[tile];
+  const int off = td.x, nsys = td.y, i0 = td.z;
+  const long long ntot = P.ntot;
+  const int hn = P.hn;
+
+  // ---- 1. load ----------------------------------------------------------
+  for (int idx = tid; idx < 2 * Q * (W + 2 * HF); idx += NT) {
+    const int r = idx / (W + 2 * HF);
+    const int c = idx - r * (W + 2 * HF);
+    const int node = wrap(i0 - HF + c, nsys);
+    S.f[r][c] = A.f_prev[(long long)r * ntot + off + node];
+  }
+  const double* mn = A.mom_in;
+  for (int c = tid; c < W + 2 * hn; c += NT) S.n[c] = mn[off + wrap(i0 - hn + c, nsys)];
+  for (int c = tid; c < W + 4; c += NT) {
+    const int node = off + wrap(i0 - 2 + c, nsys);
+    S.u[c] = mn[ntot + node];
+    S.T[c] = mn[2 * ntot + node];
+  }
+  __syncthreads();
+
+  // ---- 2. contact value on tile +-2, WENO-5 faces ------------------------
+  for (int c = tid; c < W + 4; c += NT) {
+    const int cn = c + hn - 2;
+    double nb = 0.0;
+    for (int j = -P.ms; j <= P.ms; ++j) nb += P.savg[j + P.ms] * S.n[cn + j];
+    const double eta = P.eta_c * nb;
+    const double om = 1.0 - eta;
+    const double chi = (2.0 - eta) / (2.0 * om * om * om);
+    const double nn = S.n[cn];
+    S.chi[c] = chi;
+    S.X[c] = nn * nn * chi * S.T[c];
+  }
+  if (P.term_mask & EVLB_TERM_ADV) {
+    for (int idx = tid; idx < 2 * Q * (W + 1); idx += NT) {
+      const int r = idx / (W + 1);
+      const int jf = idx - r * (W + 1);      // face i0 + jf - 1/2
+      const int k = r < Q ? r : r - Q;
+      const bool pos = k >= Q / 2;             // p_k > 0: upwind from the left
+      const double* fr = &S.f[r][0];
+      double v0, v1, v2, v3, v4;
+      if (pos) {
+        v0 = fr[jf]; v1 = fr[jf + 1]; v2 = fr[jf + 2]; v3 = fr[jf + 3]; v4 = fr[jf + 4];
+      } else {
+        v0 = fr[jf + 5]; v1 = fr[jf + 4]; v2 = fr[jf + 3]; v3 = fr[jf + 2]; v4 = fr[jf + 1];
+      }
+      S.flux[r][jf] = weno5(v0, v1, v2, v3, v4, P.weno_eps);
+    }
+  }
+  __syncthreads();
+
+  // ---- 3. node fields ----------------------------------------------------
+  if (tid < W) {
+    const int j = tid;
+    const int c = j + 2;          // index in the +-2 windows
+    const int cn = j + hn;        // index in the density window
+    const double n = S.n[cn];
+    const double u = S.u[c];
+    const double T = S.T[c];
+    const double chi = S.chi[c];
+    const double q = mn[3 * ntot + off + wrap(i0 + j, nsys)];
+    const double idx12 = P.inv_dx * (1.0 / 12.0);
+    double Fx = P.g_ext;
+    if (P.force_model == EVLB_FORCE_EV1) {
+      double s = 0.0;
+      for (int m = 1; m <= P.mf; ++m) s += P.cfor[m - 1] * (S.n[cn + m] - S.n[cn - m]);
+      Fx += s;
+    } else if (P.force_model == EVLB_FORCE_EV2) {
+      const double d1 = (S.n[cn - 2] - 8.0 * S.n[cn - 1] + 8.0 * S.n[cn + 1] - S.n[cn + 2]) * idx12;
+      const double d3 = (-S.n[cn - 2] + 2.0 * S.n[cn - 1] - 2.0 * S.n[cn + 1] + S.n[cn + 2]) *
+                        (0.5 * P.inv_dx * P.inv_dx * P.inv_dx);
+      Fx += P.two_a * d1 + P.kappa * d3;
+    }
+    const double X = S.X[c];
+    const double Ag = (S.X[c - 2] - 8.0 * S.X[c - 1] + 8.0 * S.X[c + 1] - S.X[c + 2]) * idx12 / X;
+    const double Bg = (S.T[c - 2] - 8.0 * S.T[c - 1] + 8.0 * S.T[c + 1] - S.T[c + 2]) * idx12 / T;
+    const double Ug = (S.u[c - 2] - 8.0 * S.u[c - 1] + 8.0 * S.u[c + 1] - S.u[c + 2]) * idx12;
+    // transport: mu (eq:viscosity), tau (eq:tau), Pr (eq:prandtl); rate chi/tau
+    const double bn = P.b * n;
+    const double y = bn * chi;
+    const double mu0 = P.mu0c * sqrt(T);
+    const double c12 = 0.16 * (1.0 + 12.0 / M_PI);
+    const double c32 = 0.36 * (1.0 + 32.0 / (9.0 * M_PI));
+    const double mu = mu0 * (1.0 / chi + 0.8 * bn + c12 * bn * bn * chi);
+    const double nu = chi * n * T * (1.0 + 0.4 * y) / mu;
+    const double Pr = (2.0 / 3.0) * (1.0 + 0.6 * y) * (1.0 + 0.8 * y + c12 * y * y) /
+                      ((1.0 + 0.4 * y) * (1.0 + 1.2 * y + c32 * y * y));
+    S.nf[NF_N][j] = n;
+    S.nf[NF_U][j] = u;
+    S.nf[NF_T][j] = T;
+    S.nf[NF_NU][j] = nu;
+    S.nf[NF_S][j] = (1.0 - Pr) * q / (5.0 * n * T * T);
+    S.nf[NF_PRE][j] = -bn * chi;
+    S.nf[NF_A][j] = Ag;
+    S.nf[NF_B][j] = Bg;
+    S.nf[NF_U1][j] = Ug;
+    S.nf[NF_FX][j] = Fx;
+  }
+  __syncthreads();
+
+  // ---- 4. update -----------------------------------------------------------
+  const int j = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int kbase = wv * VPT;
+  const bool valid = (i0 + j) < nsys;
+  const long long gnode = off + i0 + j;
+  double pm[6] = {0, 0, 0, 0, 0, 0};
+  {
+    const double n = S.nf[NF_N][j], u = S.nf[NF_U][j], T = S.nf[NF_T][j];
+    const double nu = S.nf[NF_NU][j], sS = S.nf[NF_S][j], pre = S.nf[NF_PRE][j];
+    const double Ag = S.nf[NF_A][j], Bg = S.nf[NF_B][j], Ug = S.nf[NF_U1][j];
+    const double Fx = S.nf[NF_FX][j];
+    const double invT = 1.0 / T;
+
+    // Hermite equilibrium E_k = sum_l meq[k][l] a_l with
+    // a_0 = n, a_1 = n u, a_{l+1} = u a_l + l (T - 1) a_{l-1}
+    double E[VPT];
+    {
+      double am = n, a = n * u;
+#pragma unroll
+      for (int v = 0; v < VPT; ++v) E[v] = P.meq[(kbase + v) * Q] * am + P.meq[(kbase + v) * Q + 1] * a;
+      const double tm1 = T - 1.0;
+#pragma unroll
+      for (int l = 1; l < Q - 1; ++l) {
+        const double an = u * a + (double)l * tm1 * am;
+        am = a;
+        a = an;
+#pragma unroll
+        for (int v = 0; v < VPT; ++v) E[v] += P.meq[(kbase + v) * Q + l + 1] * a;
+      }
+    }
+    // momentum derivative (Dp F)_k, (Dp G)_k
+    double dF[VPT], dG[VPT];
+#pragma unroll
+    for (int v = 0; v < VPT; ++v) { dF[v] = 0.0; dG[v] = 0.0; }
+    if (P.term_mask & EVLB_TERM_FORCE) {
+#pragma unroll
+      for (int kp = 0; kp < Q; ++kp) {
+        const double fk = S.f[kp][j + HF];
+        const double gk = S.f[Q + kp][j + HF];
+#pragma unroll
+        for (int v = 0; v < VPT; ++v) {
+          const double d = P.dpm[(kbase + v) * Q + kp];
+          dF[v] += d * fk;
+          dG[v] += d * gk;
+        }
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < VPT; ++v) {
+      const int k = kbase + v;
+      const double pk = P.vel[k];
+      const double F = S.f[k][j + HF];
+      const double G = S.f[Q + k][j + HF];
+      const double xi = pk - u;
+      const double th = xi * xi * invT;
+      double LF = 0.0, LG = 0.0;
+      if (P.term_mask & EVLB_TERM_ADV) {
+        LF = -pk * (S.flux[k][j + 1] - S.flux[k][j]) * P.inv_dx;
+        LG = -pk * (S.flux[Q + k][j + 1] - S.flux[Q + k][j]) * P.inv_dx;
+      }
+      if (P.term_mask & EVLB_TERM_FORCE) {
+        LF -= Fx * dF[v];
+        LG -= Fx * dG[v];
+      }
+      if (P.term_mask & EVLB_TERM_J0) {
+        const double FS = E[v] * (1.0 + sS * xi * (th - 3.0));
+        const double GS = T * E[v] * (1.0 + sS * xi * (th - 1.0));
+        LF -= nu * (F - FS);
+        LG -= nu * (G - GS);
+      }
+      if (P.term_mask & EVLB_TERM_J1) {
+        LF += pre * E[v] * (xi * (Ag + 0.3 * (th - 3.0) * Bg) + 0.6 * (th - 1.0) * Ug);
+        LG += pre * T * E[v] * (xi * (Ag + 0.3 * (th - 1.0) * Bg) + 0.2 * (3.0 * th - 1.0) * Ug);
+      }
+      double Fo, Go;
+      if (A.rhs_mode) {
+        Fo = LF;
+        Go = LG;
+      } else {
+        double Fn = F, Gn = G;
+        if (!A.first && valid) {
+          Fn = A.f_n[(long long)k * ntot + gnode];
+          Gn = A.f_n[(long long)(Q + k) * ntot + gnode];
+        }
+        Fo = A.alpha * Fn + A.beta * (F + P.dt * LF);
+        Go = A.alpha * Gn + A.beta * (G + P.dt * LG);
+      }
+      if (valid) {
+        A.f_out[(long long)k * ntot + gnode] = Fo;
+        A.f_out[(long long)(Q + k) * ntot + gnode] = Go;
+      }
+      const double p2 = pk * pk;
+      pm[0] += Fo;
+      pm[1] += pk * Fo;
+      pm[2] += p2 * Fo;
+      pm[3] += p2 * pk * Fo;
+      pm[4] += Go;
+      pm[5] += pk * Go;
+    }
+  }
+  if (A.rhs_mode) {
+    __syncthreads();
+    return;
+  }
+  __syncthreads();  // faces (aliased by red) fully consumed
+#pragma unroll
+  for (int m = 0; m < 6; ++m) S.red[wv][m][j] = pm[m];
+  __syncthreads();
+
+  // ---- 5. moments of the new state --------------------------------------
+  if (tid < W && (i0 + tid) < nsys) {
+    double s[6];
+#pragma unroll
+    for (int m = 0; m < 6; ++m) {
+      double acc = 0.0;
+#pragma unroll
+      for (int w = 0; w < NW; ++w) acc += S.red[w][m][tid];
+      s[m] = acc;
+    }
+    const double n = s[0];
+    const double u = s[1] / n;
+    const double T = (2.0 / 3.0) * (0.5 * s[2] + s[4] - 0.5 * n * u * u) / n;
+    const double x3 = s[3] - 3.0 * u * s[2] + 3.0 * u * u * s[1] - u * u * u * s[0];
+    const double q = 0.5 * x3 + s[5] - u * s[4];
+    const long long g = off + i0 + tid;
+    A.mom_out[g] = n;
+    A.mom_out[ntot + g] = u;
+    A.mom_out[2 * ntot + g] = T;
+    A.mom_out[3 * ntot + g] = q;
+    if (!(n > 0.0) || !(T > 0.0) || !isfinite(n) || !isfinite(T) || !isfinite(q) || !isfinite(u))
+      P.status[0] = 1;
+  }
+  __syncthreads();
+}
+
+template <int Q, int NW>
+__global__ __launch_bounds__(64 * NW) void stage_kernel(DevParams P, StageArgs A) {
+  __shared__ Smem<Q, NW> S;
+  for (int t = blockIdx.x; t < P.ntiles; t += gridDim.x) stage_tile<Q, NW>(P, A, t, S);
+}
+
+// Grid-wide barrier for the persistent kernel (all workgroups co-resident:
+// cooperative launch).  Agent-scope release/acquire makes the stage's global
+// writes of every XCD visible to all others.  The wait is bounded: on time-out
+// the abort latch is set and every workgroup leaves its step loop.
+__device__ bool grid_barrier(const DevParams& P, unsigned nblocks) {
+  __syncthreads();
+  __shared__ int s_abort;
+  if (threadIdx.x == 0) {
+    unsigned* count = P.bar;
+    unsigned* gen = P.bar + 1;
+    const unsigned g = __hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __atomic_thread_fence(__ATOMIC_RELEASE);
+    const unsigned arrived = __hip_atomic_fetch_add(count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    int abort = 0;
+    if (arrived == nblocks - 1) {
+      __hip_atomic_store(count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_fetch_add(gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      long long spins = 0;
+      while (__hip_atomic_load(gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
+        __builtin_amdgcn_s_sleep(1);
+        if (++spins > (1ll << 22)) {
+          __hip_atomic_store(P.status + 1, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          break;
+        }
+        if (__hip_atomic_load(P.status + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
+      }
+    }
+    __atomic_thread_fence(__ATOMIC_ACQUIRE);
+    abort = __hip_atomic_load(P.status + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    s_abort = abort;
+  }
+  __syncthreads();
+  return s_abort == 0;
+}
+
+// Resets the barrier counters and the abort latch (a kernel rather than a
+// memset so that the sequence stays valid under stream capture).
+__global__ void clear_barrier_kernel(DevParams P) {
+  if (threadIdx.x == 0) {
+    P.bar[0] = 0u;
+    P.bar[1] = 0u;
+    P.status[1] = 0;
+  }
+}
+
+struct PersistArgs {
+  double* f;            // f^n in/out
+  double* f1;
+  double* f2;
+  double* momA;
+  double* momB;         // momA holds the moments of f on entry
+  int nsteps;
+};
+
+template <int Q, int NW>
+__global__ __launch_bounds__(64 * NW) void persistent_kernel(DevParams P, PersistArgs R) {
+  __shared__ Smem<Q, NW> S;
+  const double a_s[3] = {0.0, 0.75, 1.0 / 3.0};
+  const double b_s[3] = {1.0, 0.25, 2.0 / 3.0};
+  for (int step = 0; step < R.nsteps; ++step) {
+    for (int s = 0; s < 3; ++s) {
+      StageArgs A;
+      A.f_prev = s == 0 ? R.f : (s == 1 ? R.f1 : R.f2);
+      A.f_n = R.f;
+      A.f_out = s == 0 ? R.f1 : (s == 1 ? R.f2 : R.f);
+      const int parity = (step * 3 + s) & 1;
+      A.mom_in = parity ? R.momB : R.momA;
+      A.mom_out = parity ? R.momA : R.momB;
+      A.alpha = a_s[s];
+      A.beta = b_s[s];
+      A.first = s == 0;
+      A.rhs_mode = 0;
+      for (int t = blockIdx.x; t < P.ntiles; t += gridDim.x) stage_tile<Q, NW>(P, A, t, S);
+      if (!grid_barrier(P, gridDim.x)) return;
+    }
+  }
+}
+
+// Moments of a state, one thread per node (also the entry moments of a step).
+template <int Q>
+__global__ __launch_bounds__(256) void moments_kernel(DevParams P, const double* __restrict__ f,
+                                                      double* __restrict__ n_out, double* __restrict__ u_out,
+                                                      double* __restrict__ T_out, double* __restrict__ q_out) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= P.ntot) return;
+  const long long nt = P.ntot;
+  double F[Q], G[Q];
+  double n = 0.0, m1 = 0.0;
+#pragma unroll
+  for (int k = 0; k < Q; ++k) {
+    F[k] = f[k * nt + i];
+    G[k] = f[(Q + k) * nt + i];
+    n += F[k];
+    m1 += P.vel[k] * F[k];
+  }
+  const double u = m1 / n;
+  double e = 0.0, q = 0.0;
+#pragma unroll
+  for (int k = 0; k < Q; ++k) {
+    const double xi = P.vel[k] - u;
+    const double ek = 0.5 * xi * xi * F[k] + G[k];
+    e += ek;
+    q += xi * ek;
+  }
+  const double T = (2.0 / 3.0) * e / n;
+  n_out[i] = n;
+  u_out[i] = u;
+  T_out[i] = T;
+  if (q_out) q_out[i] = q;
+}
+
+// Reduced Maxwellian F = E(n, u, T), G = T E, one thread per node.
+template <int Q>
+__global__ __launch_bounds__(256) void equilibrium_kernel(DevParams P, const double* __restrict__ n_in,
+                                                          const double* __restrict__ u_in,
+                                                          const double* __restrict__ T_in,
+                                                          double* __restrict__ f) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= P.ntot) return;
+  const long long nt = P.ntot;
+  const double n = n_in[i], u = u_in[i], T = T_in[i];
+  double a[Q];
+  a[0] = n;
+  a[1] = n * u;
+#pragma unroll
+  for (int l = 1; l < Q - 1; ++l) a[l + 1] = u * a[l] + (double)l * (T - 1.0) * a[l - 1];
+#pragma unroll
+  for (int k = 0; k < Q; ++k) {
+    double E = 0.0;
+#pragma unroll
+    for (int l = 0; l < Q; ++l) E += P.meq[k * Q + l] * a[l];
+    f[k * nt + i] = E;
+    f[(Q + k) * nt + i] = T * E;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct Layout {
+  size_t tables, tiles, f1, f2, momA, momB, status, total;
+  long long ntot;
+  int ntiles, ms, mf;
+};
+
+int count_tiles(const evlb_params* p) {
+  int t = 0;
+  for (int s = 0; s < p->n_sys; ++s) t += (p->nx[s] + W - 1) / W;
+  return t;
+}
+
+bool is_even_multiple(double a, double dx, int* m) {
+  const double r = a / dx;
+  const long long k = llround(r);
+  if (k <= 0 || std::fabs(r - (double)k) > 1e-9 * r || (k & 1)) return false;
+  *m = (int)k;
+  return true;
+}
+
+int validate(const evlb_params* p) {
+  if (!p) return EVLB_EINVAL;
+  if (p->abi_version != EVLB_ABI_VERSION) return EVLB_EINVAL;
+  if (p->dim != 1) return EVLB_EUNSUPPORTED;
+  if (p->n_sys < 1 || !p->nx) return EVLB_EINVAL;
+  long long ntot = 0;
+  for (int s = 0; s < p->n_sys; ++s) {
+    if (p->nx[s] < 8) return EVLB_EINVAL;
+    ntot += p->nx[s];
+  }
+  if (ntot > (1ll << 31) - 1) return EVLB_EINVAL;
+  if (p->q != 8 && p->q != 16 && p->q != 24) return EVLB_EUNSUPPORTED;
+  if (!(p->dx > 0) || !(p->dt > 0) || !std::isfinite(p->dx) || !std::isfinite(p->dt)) return EVLB_EINVAL;
+  if (!(p->sigma > 0) || !(p->phi_sigma >= 0) || !std::isfinite(p->phi_sigma)) return EVLB_EINVAL;
+  if (!(p->gamma > 3.0)) return EVLB_EINVAL;
+  if (p->force_model == EVLB_FORCE_EV2 && !(p->gamma > 5.0)) return EVLB_EINVAL;
+  if (p->force_model < 0 || p->force_model > 2) return EVLB_EINVAL;
+  if (p->term_mask & ~EVLB_TERM_ALL) return EVLB_EINVAL;
+  if (!(p->weno_eps > 0) || !std::isfinite(p->g_ext)) return EVLB_EINVAL;
+  if (p->exec_mode < 0 || p->exec_mode > 2) return EVLB_EINVAL;
+  int ms, mf = 0;
+  if (!is_even_multiple(p->sigma, p->dx, &ms) || ms > MS_MAX) return EVLB_EINVAL;
+  if (p->force_model == EVLB_FORCE_EV1) {
+    if (!is_even_multiple(p->r_cut, p->dx, &mf) || mf > MF_MAX) return EVLB_EINVAL;
+  }
+  // stability of WENO-5 + TVD-RK3 advection: CFL number <= 1
+  std::vector<double> v, w;
+  evlb::gauss_hermite_nodes(p->q, v, w);
+  if (p->dt * v.back() / p->dx > 1.0) return EVLB_ECFL;
+  return EVLB_OK;
+}
+
+Layout make_layout(const evlb_params* p) {
+  Layout L{};
+  L.ntot = 0;
+  for (int s = 0; s < p->n_sys; ++s) L.ntot += p->nx[s];
+  L.ntiles = count_tiles(p);
+  L.ms = (int)llround(p->sigma / p->dx);
+  L.mf = p->force_model == EVLB_FORCE_EV1 ? (int)llround(p->r_cut / p->dx) : 0;
+  const int q = p->q;
+  size_t off = 0;
+  L.tables = off;
+  off += align256(sizeof(double) * (size_t)(q + 2 * q * q + 2 * L.ms + 1 + (L.mf > 0 ? L.mf : 1)));
+  L.tiles = off;
+  off += align256(sizeof(int4) * (size_t)L.ntiles);
+  const size_t fbytes = align256(sizeof(double) * 2 * (size_t)q * (size_t)L.ntot);
+  L.f1 = off; off += fbytes;
+  L.f2 = off; off += fbytes;
+  const size_t mbytes = align256(sizeof(double) * 4 * (size_t)L.ntot);
+  L.momA = off; off += mbytes;
+  L.momB = off; off += mbytes;
+  L.status = off; off += 256;
+  L.total = off;
+  return L;
+}
+
+}  // namespace
+
+struct evlb_ctx {
+  evlb_params p;
+  std::vector<int32_t> nx;
+  std::vector<double> vel;
+  Layout L;
+  DevParams dp;
+  char* ws;
+  int device;
+  int cus;
+};
+
+namespace {
+
+#define EVLB_HIP(call)                         \
+  do {                                         \
+    if ((call) != hipSuccess) return EVLB_EHIP; \
+  } while (0)
+
+template <int Q, int NW>
+int launch_stage(evlb_ctx* c, const StageArgs& A, hipStream_t st) {
+  hipLaunchKernelGGL((stage_kernel<Q, NW>), dim3(c->L.ntiles), dim3(64 * NW), 0, st, c->dp, A);
+  return hipGetLastError() == hipSuccess ? EVLB_OK : EVLB_EHIP;
+}
+
+template <int Q, int NW>
+int launch_persistent(evlb_ctx* c, double* f, int nsteps, hipStream_t st) {
+  int per_cu = 0;
+  EVLB_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, persistent_kernel<Q, NW>, 64 * NW, 0));
+  if (per_cu < 1) return EVLB_EHIP;
+  int grid = per_cu * c->cus;
+  if (grid > c->L.ntiles) grid = c->L.ntiles;
+  PersistArgs R;
+  R.f = f;
+  R.f1 = (double*)(c->ws + c->L.f1);
+  R.f2 = (double*)(c->ws + c->L.f2);
+  R.momA = (double*)(c->ws + c->L.momA);
+  R.momB = (double*)(c->ws + c->L.momB);
+  R.nsteps = nsteps;
+  hipLaunchKernelGGL(clear_barrier_kernel, dim3(1), dim3(64), 0, st, c->dp);
+  EVLB_HIP(hipGetLastError());
+  DevParams P = c->dp;
+  void* args[] = {&P, &R};
+  EVLB_HIP(hipLaunchCooperativeKernel((const void*)persistent_kernel<Q, NW>, dim3(grid), dim3(64 * NW), args, 0,
+                                      st));
+  return EVLB_OK;
+}
+
+template <int Q>
+struct QCfg;
+template <>
+struct QCfg<8> { static constexpr int NW = 4; };
+template <>
+struct QCfg<16> { static constexpr int NW = 8; };
+template <>
+struct QCfg<24> { static constexpr int NW = 8; };
+
+template <int Q>
+int run_moments(evlb_ctx* c, const double* f, double* n, double* u, double* T, double* q, hipStream_t st) {
+  const long long nt = c->L.ntot;
+  const int blocks = (int)((nt + 255) / 256);
+  hipLaunchKernelGGL((moments_kernel<Q>), dim3(blocks), dim3(256), 0, st, c->dp, f, n, u, T, q);
+  return hipGetLastError() == hipSuccess ? EVLB_OK : EVLB_EHIP;
+}
+
+template <int Q>
+int run_step(evlb_ctx* c, double* f, int nsteps, hipStream_t st) {
+  constexpr int NW = QCfg<Q>::NW;
+  const long long nt = c->L.ntot;
+  double* momA = (double*)(c->ws + c->L.momA);
+  double* momB = (double*)(c->ws + c->L.momB);
+  int rc = run_moments<Q>(c, f, momA, momA + nt, momA + 2 * nt, momA + 3 * nt, st);
+  if (rc) return rc;
+  int mode = c->p.exec_mode;
+  if (mode == EVLB_EXEC_AUTO) mode = (c->L.ntiles <= 2 * c->cus) ? EVLB_EXEC_PERSISTENT : EVLB_EXEC_PER_STAGE;
+  if (mode == EVLB_EXEC_PERSISTENT) return launch_persistent<Q, NW>(c, f, nsteps, st);
+  double* f1 = (double*)(c->ws + c->L.f1);
+  double* f2 = (double*)(c->ws + c->L.f2);
+  const double a_s[3] = {0.0, 0.75, 1.0 / 3.0};
+  const double b_s[3] = {1.0, 0.25, 2.0 / 3.0};
+  for (int step = 0; step < nsteps; ++step) {
+    for (int s = 0; s < 3; ++s) {
+      StageArgs A;
+      A.f_prev = s == 0 ? f : (s == 1 ? f1 : f2);
+      A.f_n = f;
+      A.f_out = s == 0 ? f1 : (s == 1 ? f2 : f);
+      const int parity = (step * 3 + s) & 1;
+      A.mom_in = parity ? momB : momA;
+      A.mom_out = parity ? momA : momB;
+      A.alpha = a_s[s];
+      A.beta = b_s[s];
+      A.first = s == 0;
+      A.rhs_mode = 0;
+      rc = launch_stage<Q, NW>(c, A, st);
+      if (rc) return rc;
+    }
+  }
+  return EVLB_OK;
+}
+
+template <int Q>
+int run_rhs(evlb_ctx* c, const double* f, double* L, hipStream_t st) {
+  constexpr int NW = QCfg<Q>::NW;
+  const long long nt = c->L.ntot;
+  double* momA = (double*)(c->ws + c->L.momA);
+  double* momB = (double*)(c->ws + c->L.momB);
+  int rc = run_moments<Q>(c, f, momA, momA + nt, momA + 2 * nt, momA + 3 * nt, st);
+  if (rc) return rc;
+  StageArgs A;
+  A.f_prev = f;
+  A.f_n = f;
+  A.f_out = L;
+  A.mom_in = momA;
+  A.mom_out = momB;
+  A.alpha = 0.0;
+  A.beta = 1.0;
+  A.first = 1;
+  A.rhs_mode = 1;
+  return launch_stage<Q, NW>(c, A, st);
+}
+
+template <int Q>
+int run_equilibrium(evlb_ctx* c, const double* n, const double* u, const double* T, double* f, hipStream_t st) {
+  const int blocks = (int)((c->L.ntot + 255) / 256);
+  hipLaunchKernelGGL((equilibrium_kernel<Q>), dim3(blocks), dim3(256), 0, st, c->dp, n, u, T, f);
+  return hipGetLastError() == hipSuccess ? EVLB_OK : EVLB_EHIP;
+}
+
+#define EVLB_DISPATCH_Q(q, fn, ...)              \
+  switch (q) {                                   \
+    case 8: return fn<8>(__VA_ARGS__);           \
+    case 16: return fn<16>(__VA_ARGS__);         \
+    case 24: return fn<24>(__VA_ARGS__);         \
+    default: return EVLB_EUNSUPPORTED;           \
+  }
+
+bool device_matches(const evlb_ctx* c) {
+  int d = -1;
+  return hipGetDevice(&d) == hipSuccess && d == c->device;
+}
+
+}  // namespace
+
+extern "C" {
+
+int evlb_validate(const evlb_params* params) { return validate(params); }
+
+size_t evlb_workspace_bytes(const evlb_params* params) {
+  if (validate(params) != EVLB_OK) return 0;
+  return make_layout(params).total;
+}
+
+int evlb_init(const evlb_params* params, void* d_workspace, size_t ws_bytes, void* hip_stream, evlb_ctx** out) {
+  if (!out) return EVLB_EINVAL;
+  *out = nullptr;
+  int rc = validate(params);
+  if (rc) return rc;
+  const Layout L = make_layout(params);
+  if (!d_workspace || ws_bytes < L.total || ((uintptr_t)d_workspace & 255)) return EVLB_EWORKSPACE;
+  evlb_ctx* c = new (std::nothrow) evlb_ctx();
+  if (!c) return EVLB_EINVAL;
+  c->p = *params;
+  c->nx.assign(params->nx, params->nx + params->n_sys);
+  c->p.nx = c->nx.data();
+  c->L = L;
+  c->ws = (char*)d_workspace;
+  if (hipGetDevice(&c->device) != hipSuccess) { delete c; return EVLB_EHIP; }
+  if (hipDeviceGetAttribute(&c->cus, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess) {
+    delete c;
+    return EVLB_EHIP;
+  }
+  evlb::TableParams tp{params->q, params->dx, params->sigma, params->phi_sigma, params->gamma, params->r_cut};
+  evlb::HostTables t;
+  evlb::build_tables(tp, t);
+  if (params->force_model != EVLB_FORCE_EV1) t.cfor.assign(1, 0.0);
+  c->vel = t.vel;
+  const int q = params->q;
+  std::vector<double> host;
+  host.insert(host.end(), t.vel.begin(), t.vel.end());
+  host.insert(host.end(), t.meq.begin(), t.meq.end());
+  host.insert(host.end(), t.dpm.begin(), t.dpm.end());
+  host.insert(host.end(), t.savg.begin(), t.savg.end());
+  host.insert(host.end(), t.cfor.begin(), t.cfor.end());
+  std::vector<int4> tiles;
+  tiles.reserve(L.ntiles);
+  int off = 0;
+  for (int s = 0; s < params->n_sys; ++s) {
+    for (int i0 = 0; i0 < params->nx[s]; i0 += W) tiles.push_back(make_int4(off, params->nx[s], i0, 0));
+    off += params->nx[s];
+  }
+  hipStream_t st = (hipStream_t)hip_stream;
+  double* tab = (double*)(c->ws + L.tables);
+  // synchronous copies: the host vectors die when this call returns
+  if (hipMemcpy(tab, host.data(), host.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(c->ws + L.tiles, tiles.data(), tiles.size() * sizeof(int4), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemset(c->ws + L.status, 0, 256) != hipSuccess) {
+    delete c;
+    return EVLB_EHIP;
+  }
+  (void)st;
+  DevParams& d = c->dp;
+  d.vel = tab;
+  d.meq = tab + q;
+  d.dpm = tab + q + q * q;
+  d.savg = tab + q + 2 * q * q;
+  d.cfor = tab + q + 2 * q * q + 2 * L.ms + 1;
+  d.tiles = (const int4*)(c->ws + L.tiles);
+  d.ntiles = L.ntiles;
+  d.ms = L.ms;
+  d.mf = L.mf;
+  d.hn = L.mf > L.ms + 2 ? L.mf : L.ms + 2;
+  d.ntot = L.ntot;
+  d.dx = params->dx;
+  d.inv_dx = 1.0 / params->dx;
+  d.dt = params->dt;
+  const double sg = params->sigma;
+  d.b = 2.0 * M_PI * sg * sg * sg / 3.0;
+  d.eta_c = M_PI * sg * sg * sg / 6.0;
+  d.mu0c = 5.0 / (16.0 * sg * sg * std::sqrt(M_PI));
+  d.weno_eps = params->weno_eps;
+  d.g_ext = params->g_ext;
+  const double g = params->gamma;
+  d.two_a = 2.0 * (2.0 * M_PI * sg * sg * sg / 3.0) * params->phi_sigma * g / (g - 3.0);
+  d.kappa = (2.0 * M_PI * std::pow(sg, 5) / 15.0) * params->phi_sigma * (g > 5.0 ? g / (g - 5.0) : 0.0);
+  d.force_model = params->force_model;
+  d.term_mask = params->term_mask;
+  d.status = (int*)(c->ws + L.status);
+  d.bar = (unsigned*)(c->ws + L.status + 64);
+  *out = c;
+  return EVLB_OK;
+}
+
+int evlb_set_equilibrium(evlb_ctx* ctx, const double* d_n, const double* d_u, const double* d_T, double* d_f,
+                         void* hip_stream) {
+  if (!ctx || !d_n || !d_u || !d_T || !d_f) return EVLB_EINVAL;
+  if (!device_matches(ctx)) return EVLB_EINVAL;
+  EVLB_DISPATCH_Q(ctx->p.q, run_equilibrium, ctx, d_n, d_u, d_T, d_f, (hipStream_t)hip_stream);
+}
+
+int evlb_step(evlb_ctx* ctx, double* d_f, int32_t nsteps, void* hip_stream) {
+  if (!ctx || !d_f || nsteps < 0) return EVLB_EINVAL;
+  if (!device_matches(ctx)) return EVLB_EINVAL;
+  if (nsteps == 0) return EVLB_OK;
+  EVLB_DISPATCH_Q(ctx->p.q, run_step, ctx, d_f, nsteps, (hipStream_t)hip_stream);
+}
+
+int evlb_rhs(evlb_ctx* ctx, const double* d_f, double* d_L, void* hip_stream) {
+  if (!ctx || !d_f || !d_L || d_f == d_L) return EVLB_EINVAL;
+  if (!device_matches(ctx)) return EVLB_EINVAL;
+  EVLB_DISPATCH_Q(ctx->p.q, run_rhs, ctx, d_f, d_L, (hipStream_t)hip_stream);
+}
+
+int evlb_moments(evlb_ctx* ctx, const double* d_f, double* d_n, double* d_u, double* d_T, double* d_q,
+                 void* hip_stream) {
+  if (!ctx || !d_f || !d_n || !d_u || !d_T) return EVLB_EINVAL;
+  if (!device_matches(ctx)) return EVLB_EINVAL;
+  EVLB_DISPATCH_Q(ctx->p.q, run_moments, ctx, d_f, d_n, d_u, d_T, d_q, (hipStream_t)hip_stream);
+}
+
+int evlb_status(evlb_ctx* ctx, void* hip_stream, int32_t clear) {
+  if (!ctx) return EVLB_EINVAL;
+  hipStream_t st = (hipStream_t)hip_stream;
+  if (hipStreamSynchronize(st) != hipSuccess) return EVLB_EHIP;
+  int h[2] = {0, 0};
+  if (hipMemcpy(h, ctx->dp.status, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess) return EVLB_EHIP;
+  if (clear && hipMemset(ctx->dp.status, 0, sizeof(h)) != hipSuccess) return EVLB_EHIP;
+  if (h[1]) return EVLB_EHIP;
+  return h[0] ? EVLB_ENONFINITE : EVLB_OK;
+}
+
+int evlb_info(const evlb_ctx* ctx, int64_t* n_tot, double* h_velocities) {
+  if (!ctx) return EVLB_EINVAL;
+  if (n_tot) *n_tot = ctx->L.ntot;
+  if (h_velocities) std::memcpy(h_velocities, ctx->vel.data(), ctx->vel.size() * sizeof(double));
+  return EVLB_OK;
+}
+
+void evlb_destroy(evlb_ctx* ctx) { delete ctx; }
+
+const char* evlb_strerror(int code) {
+  switch (code) {
+    case EVLB_OK: return "ok";
+    case EVLB_EINVAL: return "invalid argument or parameter";
+    case EVLB_ECFL: return "time step above the advection stability limit";
+    case EVLB_EWORKSPACE: return "workspace missing, too small or not 256-byte aligned";
+    case EVLB_EHIP: return "HIP runtime error";
+    case EVLB_ENONFINITE: return "non-positive or non-finite density or temperature";
+    case EVLB_EUNSUPPORTED: return "unsupported configuration";
+    default: return "unknown error";
+  }
+}
+
+}  // extern "C"

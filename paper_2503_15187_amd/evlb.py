@@ -1,0 +1,219 @@
+"""Python binding of the EV-FDLB C ABI (include/evlb.h).
+
+Argument marshalling only: every step of the method runs in the HIP kernels
+of libevlb.so.  Device arrays are torch tensors (float64, on the current
+HIP device); streams are torch streams (the current stream by default).
+The functions mirror the C entry points name for name; `Solver` bundles a
+context with its workspace.
+"""
+import ctypes
+import os
+
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libevlb.so")
+
+EVLB_ABI_VERSION = 1
+EVLB_OK, EVLB_EINVAL, EVLB_ECFL, EVLB_EWORKSPACE, EVLB_EHIP, EVLB_ENONFINITE, EVLB_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
+EVLB_FORCE_EV1, EVLB_FORCE_EV2, EVLB_FORCE_NONE = 0, 1, 2
+EVLB_TERM_ADV, EVLB_TERM_FORCE, EVLB_TERM_J0, EVLB_TERM_J1, EVLB_TERM_ALL = 1, 2, 4, 8, 15
+EVLB_EXEC_AUTO, EVLB_EXEC_PER_STAGE, EVLB_EXEC_PERSISTENT = 0, 1, 2
+
+
+class evlb_params(ctypes.Structure):
+    _fields_ = [
+        ("abi_version", ctypes.c_int32),
+        ("dim", ctypes.c_int32),
+        ("n_sys", ctypes.c_int32),
+        ("nx", ctypes.POINTER(ctypes.c_int32)),
+        ("q", ctypes.c_int32),
+        ("dx", ctypes.c_double),
+        ("dt", ctypes.c_double),
+        ("sigma", ctypes.c_double),
+        ("phi_sigma", ctypes.c_double),
+        ("gamma", ctypes.c_double),
+        ("r_cut", ctypes.c_double),
+        ("force_model", ctypes.c_int32),
+        ("term_mask", ctypes.c_int32),
+        ("weno_eps", ctypes.c_double),
+        ("g_ext", ctypes.c_double),
+        ("exec_mode", ctypes.c_int32),
+    ]
+
+
+class EvlbError(RuntimeError):
+    def __init__(self, code, what=""):
+        self.code = code
+        super().__init__(f"{what}: {strerror(code)} ({code})" if what else f"{strerror(code)} ({code})")
+
+
+_lib = None
+
+_SIGS = {
+    "evlb_validate": (ctypes.c_int, [ctypes.POINTER(evlb_params)]),
+    "evlb_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(evlb_params)]),
+    "evlb_init": (ctypes.c_int, [ctypes.POINTER(evlb_params), ctypes.c_void_p, ctypes.c_size_t,
+                                 ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
+    "evlb_set_equilibrium": (ctypes.c_int, [ctypes.c_void_p] * 6),
+    "evlb_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
+    "evlb_rhs": (ctypes.c_int, [ctypes.c_void_p] * 4),
+    "evlb_moments": (ctypes.c_int, [ctypes.c_void_p] * 7),
+    "evlb_status": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32]),
+    "evlb_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64), ctypes.c_void_p]),
+    "evlb_destroy": (None, [ctypes.c_void_p]),
+    "evlb_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+}
+
+
+def lib():
+    """The loaded libevlb.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"HIP library {LIB_PATH} is not built "
+                               "(run __graft_entry__.build() or python -m paper_2503_15187_amd.build)")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def strerror(code):
+    return lib().evlb_strerror(int(code)).decode()
+
+
+def _check(code, what):
+    if code != EVLB_OK:
+        raise EvlbError(code, what)
+
+
+def make_params(q, dx, dt, nx, sigma=1.0, phi_sigma=1.0, gamma=6.0, r_cut=5.0,
+                force_model=EVLB_FORCE_EV1, term_mask=EVLB_TERM_ALL, weno_eps=1e-6,
+                g_ext=0.0, exec_mode=EVLB_EXEC_AUTO):
+    """evlb_params for one or several periodic 1D systems (nx: int or list).
+    The returned structure keeps its nx array alive."""
+    nxs = [int(nx)] if isinstance(nx, (int,)) else [int(v) for v in nx]
+    arr = (ctypes.c_int32 * len(nxs))(*nxs)
+    p = evlb_params(EVLB_ABI_VERSION, 1, len(nxs), arr, int(q), float(dx), float(dt), float(sigma),
+                    float(phi_sigma), float(gamma), float(r_cut), int(force_model), int(term_mask),
+                    float(weno_eps), float(g_ext), int(exec_mode))
+    p._nx_keepalive = arr
+    return p
+
+
+def evlb_validate(params):
+    return lib().evlb_validate(ctypes.byref(params))
+
+
+def evlb_workspace_bytes(params):
+    return lib().evlb_workspace_bytes(ctypes.byref(params))
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _dptr(t, name):
+    if t is None:
+        return None
+    if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+        raise ValueError(f"{name}: expected a contiguous float64 device tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def evlb_init(params, workspace, stream=None):
+    """Returns a context handle (int).  workspace: uint8 device tensor of at
+    least evlb_workspace_bytes(params) bytes, kept alive by the caller."""
+    if not (workspace.is_cuda and workspace.is_contiguous()):
+        raise ValueError("workspace must be a contiguous device tensor")
+    out = ctypes.c_void_p()
+    _check(lib().evlb_init(ctypes.byref(params), ctypes.c_void_p(workspace.data_ptr()),
+                           workspace.numel() * workspace.element_size(), _stream(stream),
+                           ctypes.byref(out)), "evlb_init")
+    return out.value
+
+
+def evlb_set_equilibrium(ctx, n, u, T, f, stream=None):
+    _check(lib().evlb_set_equilibrium(ctx, _dptr(n, "n"), _dptr(u, "u"), _dptr(T, "T"), _dptr(f, "f"),
+                                      _stream(stream)), "evlb_set_equilibrium")
+
+
+def evlb_step(ctx, f, nsteps, stream=None):
+    _check(lib().evlb_step(ctx, _dptr(f, "f"), int(nsteps), _stream(stream)), "evlb_step")
+
+
+def evlb_rhs(ctx, f, L, stream=None):
+    _check(lib().evlb_rhs(ctx, _dptr(f, "f"), _dptr(L, "L"), _stream(stream)), "evlb_rhs")
+
+
+def evlb_moments(ctx, f, n, u, T, q=None, stream=None):
+    _check(lib().evlb_moments(ctx, _dptr(f, "f"), _dptr(n, "n"), _dptr(u, "u"), _dptr(T, "T"),
+                              _dptr(q, "q"), _stream(stream)), "evlb_moments")
+
+
+def evlb_status(ctx, stream=None, clear=True):
+    return lib().evlb_status(ctx, _stream(stream), 1 if clear else 0)
+
+
+def evlb_info(ctx, q):
+    n = ctypes.c_int64()
+    v = (ctypes.c_double * q)()
+    _check(lib().evlb_info(ctx, ctypes.byref(n), v), "evlb_info")
+    return n.value, list(v)
+
+
+def evlb_destroy(ctx):
+    lib().evlb_destroy(ctx)
+
+
+class Solver:
+    """A context plus its workspace on the current device."""
+
+    def __init__(self, q, dx, dt, nx, device=None, stream=None, **kw):
+        self.params = make_params(q, dx, dt, nx, **kw)
+        self.q = int(q)
+        nbytes = evlb_workspace_bytes(self.params)
+        if nbytes == 0:
+            _check(evlb_validate(self.params) or EVLB_EINVAL, "evlb_workspace_bytes")
+        device = device or torch.device("cuda", torch.cuda.current_device())
+        self.device = device
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        self.ctx = evlb_init(self.params, self.workspace, stream)
+        self.n_tot, self.velocities = evlb_info(self.ctx, self.q)
+
+    def __del__(self):
+        ctx = getattr(self, "ctx", None)
+        if ctx:
+            evlb_destroy(ctx)
+            self.ctx = None
+
+    def new_state(self):
+        return torch.empty((2, self.q, self.n_tot), dtype=torch.float64, device=self.device)
+
+    def equilibrium(self, n, u, T, stream=None):
+        f = self.new_state()
+        evlb_set_equilibrium(self.ctx, n, u, T, f, stream)
+        return f
+
+    def step(self, f, nsteps, stream=None):
+        evlb_step(self.ctx, f, nsteps, stream)
+        return f
+
+    def rhs(self, f, stream=None):
+        L = torch.empty_like(f)
+        evlb_rhs(self.ctx, f, L, stream)
+        return L
+
+    def moments(self, f, stream=None):
+        out = torch.empty((4, self.n_tot), dtype=torch.float64, device=self.device)
+        evlb_moments(self.ctx, f, out[0], out[1], out[2], out[3], stream)
+        return out
+
+    def status(self, stream=None):
+        return evlb_status(self.ctx, stream)

@@ -1,0 +1,95 @@
+"""Host-side checks of the C ABI: the library loads, exports every entry
+point declared in include/evlb.h, and validates parameters on the host
+(no device call is made by any of these)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2503_15187_amd as P
+from paper_2503_15187_amd import evlb as E
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+DT16 = 0.2 * 0.125 / 6.630878198393129
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "evlb.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(evlb_[a-z_]+)\s*\(", src)))
+
+
+def test_header_symbols_exported():
+    names = declared_functions()
+    assert len(names) >= 10
+    L = P.lib()
+    for name in names:
+        assert hasattr(L, name), name
+
+
+def test_validate_accepts_workload_parameters():
+    assert P.evlb_validate(P.make_params(16, 0.125, DT16, 256)) == E.EVLB_OK
+    assert P.evlb_validate(P.make_params(24, 0.125, 0.2 * 0.125 / 8.5078, 4096)) == E.EVLB_OK
+    assert P.evlb_validate(P.make_params(16, 0.25, 0.2 * 0.25 / 6.6309, [256, 300, 8192])) == E.EVLB_OK
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(q=12), E.EVLB_EUNSUPPORTED),
+    (dict(dt=0.1), E.EVLB_ECFL),
+    (dict(dt=-1.0), E.EVLB_EINVAL),
+    (dict(dx=0.3), E.EVLB_EINVAL),            # sigma/dx not an even integer
+    (dict(r_cut=5.125), E.EVLB_EINVAL),       # r_cut/dx odd
+    (dict(r_cut=9.0), E.EVLB_EINVAL),         # window above the built maximum
+    (dict(nx=4), E.EVLB_EINVAL),
+    (dict(nx=[256, 0]), E.EVLB_EINVAL),
+    (dict(gamma=2.5), E.EVLB_EINVAL),
+    (dict(force_model=E.EVLB_FORCE_EV2, gamma=4.5), E.EVLB_EINVAL),
+    (dict(force_model=7), E.EVLB_EINVAL),
+    (dict(term_mask=16), E.EVLB_EINVAL),
+    (dict(weno_eps=0.0), E.EVLB_EINVAL),
+    (dict(exec_mode=9), E.EVLB_EINVAL),
+    (dict(sigma=-1.0), E.EVLB_EINVAL),
+])
+def test_validate_rejects(kw, code):
+    base = dict(q=16, dx=0.125, dt=DT16, nx=256)
+    base.update(kw)
+    p = P.make_params(**base)
+    assert P.evlb_validate(p) == code
+    assert P.evlb_workspace_bytes(p) == 0
+
+
+def test_abi_version_checked():
+    p = P.make_params(16, 0.125, DT16, 256)
+    p.abi_version = 99
+    assert P.evlb_validate(p) == E.EVLB_EINVAL
+
+
+def test_workspace_size_scales_with_nodes():
+    a = P.evlb_workspace_bytes(P.make_params(16, 0.125, DT16, 1024))
+    b = P.evlb_workspace_bytes(P.make_params(16, 0.125, DT16, 2048))
+    # two stage buffers [2][q][n] and two moment buffers [4][n] per node
+    per_node = 2 * 2 * 16 * 8 + 2 * 4 * 8
+    assert abs((b - a) - 1024 * per_node) < 4096
+
+
+def test_init_rejects_missing_workspace_before_device_work():
+    p = P.make_params(16, 0.125, DT16, 256)
+    out = ctypes.c_void_p()
+    L = P.lib()
+    assert L.evlb_init(ctypes.byref(p), None, 0, None, ctypes.byref(out)) == E.EVLB_EWORKSPACE
+    assert L.evlb_init(ctypes.byref(p), ctypes.c_void_p(256), 16, None, ctypes.byref(out)) == E.EVLB_EWORKSPACE
+    assert L.evlb_init(ctypes.byref(p), ctypes.c_void_p(257), 1 << 30, None, ctypes.byref(out)) == E.EVLB_EWORKSPACE
+    assert out.value is None
+
+
+def test_null_context_rejected():
+    L = P.lib()
+    assert L.evlb_step(None, None, 1, None) == E.EVLB_EINVAL
+    assert L.evlb_moments(None, None, None, None, None, None, None) == E.EVLB_EINVAL
+    assert L.evlb_status(None, None, 0) == E.EVLB_EINVAL
+
+
+def test_strerror():
+    for code in (0, -1, -2, -3, -4, -5, -6, -77):
+        assert isinstance(P.strerror(code), str) and P.strerror(code)

@@ -1,0 +1,201 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Tolerance: the method is FP64 throughout; the two sides differ only in
+summation order (and the WENO-5 weights' common denominator), so one step
+must agree to 1e-11 relative and 1000 steps to 1e-8 relative, measured as
+max |gpu - oracle| / max |oracle| over each plane (F, G) of the state.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import workloads  # noqa: E402
+from oracle import step1d  # noqa: E402
+from oracle.model import Params  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+E = None
+
+
+def setup_module(module):
+    global E
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2503_15187_amd import evlb as _E
+    E = _E
+
+
+DEV = "cuda"
+
+
+def td(a):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=DEV)
+
+
+def rel(got, ref):
+    """max over planes of max|got - ref| / max|ref|."""
+    return max(np.max(np.abs(got[i] - ref[i])) / np.max(np.abs(ref[i])) for i in range(2))
+
+
+def oracle_tables(c, **kw):
+    return step1d.Tables(Params(Q=c["Q"], dx=c["dx"], dt=c["dt"], **kw))
+
+
+def solver(c, nx=None, **kw):
+    return E.Solver(c["Q"], c["dx"], c["dt"], nx if nx is not None else c["nx"], **kw)
+
+
+def nonequilibrium(F, G, tb, seed=3):
+    rng = np.random.default_rng(seed)
+    scale = tb.w[:, None] / tb.w.max()
+    return F * (1 + 0.03 * rng.standard_normal(F.shape) * scale), G * (1 + 0.03 * rng.standard_normal(G.shape) * scale)
+
+
+def case_phase():
+    c, n, u, T = workloads.phase_separation_1d()
+    return c, n, u, T
+
+
+def case_slab(nx=1024):
+    c, n, u, T = workloads.slab_1d(nx=nx)
+    return c, n, u, T
+
+
+def test_equilibrium_and_moments_match_oracle():
+    for c, n, u, T in (case_phase(), case_slab()):
+        print(f"case Q={c['Q']} nx={c['nx']}", flush=True)
+        tb = oracle_tables(c)
+        F, G = step1d.initial_state(n, u, T, tb)
+        s = solver(c)
+        f = s.equilibrium(td(n), td(u), td(T)).cpu().numpy()
+        assert rel(f, [F, G]) < 1e-13
+        Fn, Gn = nonequilibrium(F, G, tb)
+        mom = s.moments(td(np.stack([Fn, Gn]))).cpu().numpy()
+        ref = step1d.moments(Fn, Gn, tb)
+        for i in range(4):
+            assert np.max(np.abs(mom[i] - ref[i])) <= 1e-13 * np.max(np.abs(ref[i])) + 1e-16, i
+
+
+@pytest.mark.parametrize("mask", [1, 2, 4, 8, 15])
+@pytest.mark.parametrize("which", ["phase", "slab"])
+def test_rhs_matches_oracle_per_term(mask, which):
+    c, n, u, T = case_phase() if which == "phase" else case_slab()
+    print(f"rhs case {which} mask={mask}", flush=True)
+    tb = oracle_tables(c, term_mask=mask)
+    F, G = nonequilibrium(*step1d.initial_state(n, u + 0.02 * np.sin(np.arange(len(n)) / 7.0), T, tb), tb)
+    LF, LG = step1d.rhs(F, G, tb)
+    s = solver(c, term_mask=mask)
+    L = s.rhs(td(np.stack([F, G]))).cpu().numpy()
+    assert rel(L, [LF, LG]) < 1e-11
+
+
+@pytest.mark.parametrize("mode", [1, 2])
+def test_one_and_ten_steps_match_oracle(mode):
+    for c, n, u, T in (case_phase(), case_slab()):
+        print(f"steps case Q={c['Q']} nx={c['nx']} mode={mode}", flush=True)
+        tb = oracle_tables(c)
+        F, G = step1d.initial_state(n, u, T, tb)
+        s = solver(c, exec_mode=mode)
+        f = s.equilibrium(td(n), td(u), td(T))
+        s.step(f, 1)
+        F1, G1 = step1d.rk3_step(F, G, tb)
+        assert rel(f.cpu().numpy(), [F1, G1]) < 1e-11
+        s.step(f, 9)
+        F10, G10 = step1d.run(F1, G1, tb, 9)
+        assert rel(f.cpu().numpy(), [F10, G10]) < 1e-10
+        assert s.status() == 0
+
+
+def test_phase_separation_1000_steps_match_oracle():
+    """Full phase-separation workload: 256 nodes, Q = 16, 1000 steps."""
+    c, n, u, T = case_phase()
+    tb = oracle_tables(c)
+    F, G = step1d.initial_state(n, u, T, tb)
+    F, G = step1d.run(F, G, tb, c["steps"])
+    s = solver(c)
+    f = s.equilibrium(td(n), td(u), td(T))
+    s.step(f, c["steps"])
+    err = rel(f.cpu().numpy(), [F, G])
+    print(f"1000-step rel err {err:.3e}", flush=True)
+    assert err < 1e-8
+    assert s.status() == 0
+
+
+def test_exec_modes_agree_and_repeat_bitwise():
+    c, n, u, T = case_slab(2048)
+    out = []
+    for mode in (1, 2, 1):
+        s = solver(c, exec_mode=mode)
+        f = s.equilibrium(td(n), td(u), td(T))
+        s.step(f, 20)
+        out.append(f.cpu().numpy())
+    assert np.array_equal(out[0], out[2])
+    assert rel(out[1], out[0]) < 1e-14
+
+
+def test_ragged_batch_matches_independent_oracle_runs():
+    """Several periodic systems of uneven length in one state."""
+    c, systems = workloads.batched_sweep_1d(n_sys=5, nx_max=700)
+    nxs = c["nx_list"]
+    tb = oracle_tables(c)
+    n = np.concatenate([s[0] for s in systems])
+    u = np.concatenate([s[1] for s in systems])
+    T = np.concatenate([s[2] for s in systems])
+    for mode in (1, 2):
+        s = solver(c, nx=nxs, exec_mode=mode)
+        f = s.equilibrium(td(n), td(u), td(T))
+        s.step(f, 5)
+        got = f.cpu().numpy()
+        off = 0
+        for (ni, ui, Ti), nx in zip(systems, nxs):
+            F, G = step1d.initial_state(ni, ui, Ti, tb)
+            F, G = step1d.run(F, G, tb, 5)
+            assert rel(got[:, :, off:off + nx], [F, G]) < 1e-11, (mode, nx)
+            off += nx
+
+
+def test_uniform_state_stationary_on_gpu():
+    c, n, u, T = case_phase()
+    s = solver(c)
+    nn = np.full(c["nx"], 0.3)
+    f = s.equilibrium(td(nn), td(0 * nn), td(0 * nn + 0.6))
+    f0 = f.clone()
+    s.step(f, 1000)
+    assert (f - f0).abs().max().item() <= 1e-14 * f0.abs().max().item()
+
+
+def test_conservation_on_gpu():
+    c, n, u, T = case_slab(4096)
+    s = solver(c)
+    f = s.equilibrium(td(n), td(u), td(T))
+    v = torch.tensor(s.velocities, dtype=torch.float64, device=DEV)[:, None]
+    m0 = f[0].sum().item()
+    scale = (v.abs() * f[0]).sum().item()
+    s.step(f, 500)
+    assert abs(f[0].sum().item() - m0) < 1e-13 * m0
+    assert abs((v * f[0]).sum().item()) < 1e-13 * scale
+    assert s.status() == 0
+
+
+def test_slab_full_size_ten_steps_match_oracle():
+    """Slab-evaporation workload at full size (4096 nodes, Q = 24)."""
+    c, n, u, T = workloads.slab_1d()
+    tb = oracle_tables(c)
+    F, G = step1d.initial_state(n, u, T, tb)
+    F, G = step1d.run(F, G, tb, 10)
+    s = solver(c)
+    f = s.equilibrium(td(n), td(u), td(T))
+    s.step(f, 10)
+    assert rel(f.cpu().numpy(), [F, G]) < 1e-10
+
+
+def test_nonfinite_state_is_reported():
+    c, n, u, T = case_phase()
+    s = solver(c)
+    f = s.equilibrium(td(n), td(u), td(T))
+    f[0, :, 17] = float("nan")
+    s.step(f, 1)
+    assert s.status() == E.EVLB_ENONFINITE
+    assert s.status() == 0   # latch cleared
