@@ -94,6 +94,7 @@ typedef struct {
   double weno_eps;       /* WENO-5 epsilon, 1e-6                             */
   double g_ext;          /* uniform external acceleration (tests), usually 0 */
   int32_t exec_mode;     /* EVLB_EXEC_*                                      */
+  int32_t tile_nodes;    /* nodes per workgroup tile: 0 = auto, 16 or 64     */
 } evlb_params;
 
 typedef struct evlb_ctx evlb_ctx; /* opaque, host memory */

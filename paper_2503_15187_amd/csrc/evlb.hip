@@ -71,11 +71,6 @@ struct StageArgs {
   int rhs_mode;          // write L(f_prev) instead of a stage
 };
 
-__device__ __forceinline__ int wrap(int i, int n) {
-  int r = i % n;
-  return r < 0 ? r + n : r;
-}
-
 // Classical WENO-5 (Jiang & Shu) face value from the five upwind-ordered
 // values v0..v4 = f_{i-2}..f_{i+2}; alpha_r = d_r/(eps+beta_r)^2 combined
 // over a common denominator (one division).
@@ -97,91 +92,178 @@ __device__ __forceinline__ double weno5(double v0, double v1, double v2, double 
   return (w0 * q0 + w1 * q1 + w2 * q2) / (w0 + w1 + w2);
 }
 
-template <int Q, int NW>
-struct Smem {
-  double f[2 * Q][W + 2 * HF];
-  union {
-    double flux[2 * Q][W + 1];
-    double red[NW][6][W];
-  };
-  double n[W + 2 * HN_MAX];
-  double u[W + 4], T[W + 4], chi[W + 4], X[W + 4];
-  double nf[NFIELD][W];
+// Launch shape of the stage kernel: tiles of W nodes, NG groups of
+// velocities (thread = node j x group g, NT = W * NG threads).  With W = 64
+// a velocity group is uniform over a wavefront and the constant tables are
+// read through the scalar cache; narrower tiles keep them in LDS.
+template <int Q, int W, int NG>
+struct Shape {
+  static constexpr int NT = W * NG;
+  static constexpr int VPT = Q / NG;
+  static constexpr bool UNIFORM = (W % 64) == 0;
+  static_assert(Q % NG == 0, "velocity groups must divide q");
+  static_assert(NG >= 2, "two node groups are needed for the field phase");
+  static_assert(NT <= 1024, "workgroup too large");
 };
 
+template <int Q, int W, int NG>
+struct Smem {
+  double f[2 * Q][W + 2 * HF];     // F rows then G rows, tile + WENO halo
+  union {
+    double flux[2 * Q][W + 1];     // WENO-5 face values
+    double red[NG][6][W];          // partial velocity moments
+  };
+  double n[W + 2 * HN_MAX];        // density window
+  double u[W + 4], T[W + 4], X[W + 4], chi[W + 4];
+  double a[Q][W];                  // Hermite moments of the local Maxwellian
+  union {
+    double fpart[NG][W];           // partial force sums
+    double msum[6][W];             // velocity moments of the new state
+  };
+  double nf[NFIELD][W];
+  double tab[Shape<Q, W, NG>::UNIFORM ? 1 : 2 * Q * Q + Q];  // meq, dpm, vel
+};
+
+__device__ __forceinline__ int wrapi(int i, int n) {
+  while (i < 0) i += n;
+  while (i >= n) i -= n;
+  return i;
+}
+
+template <int Q, int W, int NG>
+__device__ __forceinline__ void load_tables(const DevParams& P, Smem<Q, W, NG>& S) {
+  if constexpr (!Shape<Q, W, NG>::UNIFORM) {
+    for (int i = threadIdx.x; i < Q * Q; i += Shape<Q, W, NG>::NT) {
+      S.tab[i] = P.meq[i];
+      S.tab[Q * Q + i] = P.dpm[i];
+    }
+    for (int i = threadIdx.x; i < Q; i += Shape<Q, W, NG>::NT) S.tab[2 * Q * Q + i] = P.vel[i];
+    __syncthreads();
+  }
+}
+
 // One stage over one tile (see file header).
-template <int Q, int NW>
-__device__ void stage_tile(const DevParams& P, const StageArgs& A, int tile, Smem<Q, NW>& S) {
-  constexpr int NT = 64 * NW;
-  constexpr int VPT = Q / NW;
-  static_assert(Q % NW == 0, "velocity groups must divide q");
+template <int Q, int W, int NG>
+__device__ void stage_tile(const DevParams& P, const StageArgs& A, int tile, Smem<Q, W, NG>& S) {
+  using SH = Shape<Q, W, NG>;
+  constexpr int NT = SH::NT;
+  constexpr int VPT = SH::VPT;
   const int tid = threadIdx.x;
   const int4 td = P.tiles[tile];
   const int off = td.x, nsys = td.y, i0 = td.z;
   const long long ntot = P.ntot;
   const int hn = P.hn;
+  const int j = tid % W;
+  const int g = SH::UNIFORM ? __builtin_amdgcn_readfirstlane(tid / W) : tid / W;
+  const int kbase = g * VPT;
+  const bool valid = (i0 + j) < nsys;
+  const long long gnode = off + i0 + j;
 
   // ---- 1. load ----------------------------------------------------------
+  // RK3 base values of this thread's velocities, fetched first so that their
+  // latency overlaps the tile staging
+  double Fn[VPT], Gn[VPT];
+  const bool need_base = !A.first && !A.rhs_mode && valid;
+#pragma unroll
+  for (int v = 0; v < VPT; ++v) {
+    Fn[v] = 0.0;
+    Gn[v] = 0.0;
+    if (need_base) {
+      Fn[v] = A.f_n[(long long)(kbase + v) * ntot + gnode];
+      Gn[v] = A.f_n[(long long)(Q + kbase + v) * ntot + gnode];
+    }
+  }
   for (int idx = tid; idx < 2 * Q * (W + 2 * HF); idx += NT) {
     const int r = idx / (W + 2 * HF);
     const int c = idx - r * (W + 2 * HF);
-    const int node = wrap(i0 - HF + c, nsys);
-    S.f[r][c] = A.f_prev[(long long)r * ntot + off + node];
+    S.f[r][c] = A.f_prev[(long long)r * ntot + off + wrapi(i0 - HF + c, nsys)];
   }
   const double* mn = A.mom_in;
-  for (int c = tid; c < W + 2 * hn; c += NT) S.n[c] = mn[off + wrap(i0 - hn + c, nsys)];
+  for (int c = tid; c < W + 2 * hn; c += NT) S.n[c] = mn[off + wrapi(i0 - hn + c, nsys)];
   for (int c = tid; c < W + 4; c += NT) {
-    const int node = off + wrap(i0 - 2 + c, nsys);
+    const int node = off + wrapi(i0 - 2 + c, nsys);
     S.u[c] = mn[ntot + node];
     S.T[c] = mn[2 * ntot + node];
   }
+  double qj = 0.0;
+  if (tid >= W && tid < 2 * W) qj = mn[3 * ntot + off + wrapi(i0 + j, nsys)];
   __syncthreads();
 
-  // ---- 2. contact value on tile +-2, WENO-5 faces ------------------------
-  for (int c = tid; c < W + 4; c += NT) {
-    const int cn = c + hn - 2;
-    double nb = 0.0;
-    for (int j = -P.ms; j <= P.ms; ++j) nb += P.savg[j + P.ms] * S.n[cn + j];
-    const double eta = P.eta_c * nb;
-    const double om = 1.0 - eta;
-    const double chi = (2.0 - eta) / (2.0 * om * om * om);
-    const double nn = S.n[cn];
-    S.chi[c] = chi;
-    S.X[c] = nn * nn * chi * S.T[c];
-  }
-  if (P.term_mask & EVLB_TERM_ADV) {
-    for (int idx = tid; idx < 2 * Q * (W + 1); idx += NT) {
-      const int r = idx / (W + 1);
-      const int jf = idx - r * (W + 1);      // face i0 + jf - 1/2
-      const int k = r < Q ? r : r - Q;
-      const bool pos = k >= Q / 2;             // p_k > 0: upwind from the left
-      const double* fr = &S.f[r][0];
-      double v0, v1, v2, v3, v4;
-      if (pos) {
-        v0 = fr[jf]; v1 = fr[jf + 1]; v2 = fr[jf + 2]; v3 = fr[jf + 3]; v4 = fr[jf + 4];
-      } else {
-        v0 = fr[jf + 5]; v1 = fr[jf + 4]; v2 = fr[jf + 3]; v3 = fr[jf + 2]; v4 = fr[jf + 1];
+  // ---- 2. contact value, Hermite moments, force partial sums, WENO faces ---
+  {
+    // contact value chi(nbar) and X = n^2 chi T on the tile +-2
+    for (int c = tid; c < W + 4; c += NT) {
+      const int cn = c + hn - 2;
+      double s0 = 0.0, s1 = 0.0;
+      int jj = -P.ms;
+      for (; jj + 1 <= P.ms; jj += 2) {
+        s0 += P.savg[jj + P.ms] * S.n[cn + jj];
+        s1 += P.savg[jj + 1 + P.ms] * S.n[cn + jj + 1];
       }
-      S.flux[r][jf] = weno5(v0, v1, v2, v3, v4, P.weno_eps);
+      if (jj <= P.ms) s0 += P.savg[jj + P.ms] * S.n[cn + jj];
+      const double eta = P.eta_c * (s0 + s1);
+      const double om = 1.0 - eta;
+      const double chi = (2.0 - eta) / (2.0 * om * om * om);
+      const double nn = S.n[cn];
+      S.chi[c] = chi;
+      S.X[c] = nn * nn * chi * S.T[c];
+    }
+    // Hermite moments a_0 = n, a_1 = n u, a_{l+1} = u a_l + l (T - 1) a_{l-1}
+    if (tid >= NT - W) {
+      const int jn = tid - (NT - W);
+      const double n = S.n[jn + hn], u = S.u[jn + 2], tm1 = S.T[jn + 2] - 1.0;
+      double am = n, a = n * u;
+      S.a[0][jn] = am;
+      S.a[1][jn] = a;
+#pragma unroll
+      for (int l = 1; l < Q - 1; ++l) {
+        const double an = u * a + (double)l * tm1 * am;
+        am = a;
+        a = an;
+        S.a[l + 1][jn] = a;
+      }
+    }
+    // EV1 force: node j, chunk g of the paired taps
+    if (P.force_model == EVLB_FORCE_EV1) {
+      const int ch = (P.mf + NG - 1) / NG;
+      const int m0 = 1 + g * ch;
+      const int m1 = min(P.mf, m0 + ch - 1);
+      const int cn = j + hn;
+      double s0 = 0.0, s1 = 0.0;
+      int m = m0;
+      for (; m + 1 <= m1; m += 2) {
+        s0 += P.cfor[m - 1] * (S.n[cn + m] - S.n[cn - m]);
+        s1 += P.cfor[m] * (S.n[cn + m + 1] - S.n[cn - m - 1]);
+      }
+      if (m <= m1) s0 += P.cfor[m - 1] * (S.n[cn + m] - S.n[cn - m]);
+      S.fpart[g][j] = s0 + s1;
+    }
+    if (P.term_mask & EVLB_TERM_ADV) {
+      for (int idx = tid; idx < 2 * Q * (W + 1); idx += NT) {
+        const int r = idx / (W + 1);
+        const int jf = idx - r * (W + 1);      // face i0 + jf - 1/2
+        const int k = r < Q ? r : r - Q;
+        const bool pos = k >= Q / 2;             // p_k > 0: upwind from the left
+        const double* fr = &S.f[r][0];
+        const int b0 = pos ? jf : jf + 5;
+        const int st = pos ? 1 : -1;
+        S.flux[r][jf] = weno5(fr[b0], fr[b0 + st], fr[b0 + 2 * st], fr[b0 + 3 * st], fr[b0 + 4 * st],
+                              P.weno_eps);
+      }
     }
   }
   __syncthreads();
 
-  // ---- 3. node fields ----------------------------------------------------
+  // ---- 3. node fields: force and gradients (group 0), transport (group 1) --
   if (tid < W) {
-    const int j = tid;
-    const int c = j + 2;          // index in the +-2 windows
-    const int cn = j + hn;        // index in the density window
-    const double n = S.n[cn];
-    const double u = S.u[c];
-    const double T = S.T[c];
-    const double chi = S.chi[c];
-    const double q = mn[3 * ntot + off + wrap(i0 + j, nsys)];
+    const int c = j + 2;
+    const int cn = j + hn;
     const double idx12 = P.inv_dx * (1.0 / 12.0);
     double Fx = P.g_ext;
     if (P.force_model == EVLB_FORCE_EV1) {
       double s = 0.0;
-      for (int m = 1; m <= P.mf; ++m) s += P.cfor[m - 1] * (S.n[cn + m] - S.n[cn - m]);
+#pragma unroll
+      for (int gg = 0; gg < NG; ++gg) s += S.fpart[gg][j];
       Fx += s;
     } else if (P.force_model == EVLB_FORCE_EV2) {
       const double d1 = (S.n[cn - 2] - 8.0 * S.n[cn - 1] + 8.0 * S.n[cn + 1] - S.n[cn + 2]) * idx12;
@@ -189,63 +271,54 @@ __device__ void stage_tile(const DevParams& P, const StageArgs& A, int tile, Sme
                         (0.5 * P.inv_dx * P.inv_dx * P.inv_dx);
       Fx += P.two_a * d1 + P.kappa * d3;
     }
-    const double X = S.X[c];
-    const double Ag = (S.X[c - 2] - 8.0 * S.X[c - 1] + 8.0 * S.X[c + 1] - S.X[c + 2]) * idx12 / X;
-    const double Bg = (S.T[c - 2] - 8.0 * S.T[c - 1] + 8.0 * S.T[c + 1] - S.T[c + 2]) * idx12 / T;
-    const double Ug = (S.u[c - 2] - 8.0 * S.u[c - 1] + 8.0 * S.u[c + 1] - S.u[c + 2]) * idx12;
+    const double T = S.T[c];
+    S.nf[NF_A][j] = (S.X[c - 2] - 8.0 * S.X[c - 1] + 8.0 * S.X[c + 1] - S.X[c + 2]) * idx12 / S.X[c];
+    S.nf[NF_B][j] = (S.T[c - 2] - 8.0 * S.T[c - 1] + 8.0 * S.T[c + 1] - S.T[c + 2]) * idx12 / T;
+    S.nf[NF_U1][j] = (S.u[c - 2] - 8.0 * S.u[c - 1] + 8.0 * S.u[c + 1] - S.u[c + 2]) * idx12;
+    S.nf[NF_FX][j] = Fx;
+    S.nf[NF_N][j] = S.n[cn];
+    S.nf[NF_U][j] = S.u[c];
+    S.nf[NF_T][j] = T;
+  } else if (tid < 2 * W) {
     // transport: mu (eq:viscosity), tau (eq:tau), Pr (eq:prandtl); rate chi/tau
+    const int c = j + 2;
+    const double n = S.n[j + hn];
+    const double T = S.T[c];
+    const double chi = S.chi[c];
     const double bn = P.b * n;
     const double y = bn * chi;
     const double mu0 = P.mu0c * sqrt(T);
     const double c12 = 0.16 * (1.0 + 12.0 / M_PI);
     const double c32 = 0.36 * (1.0 + 32.0 / (9.0 * M_PI));
     const double mu = mu0 * (1.0 / chi + 0.8 * bn + c12 * bn * bn * chi);
-    const double nu = chi * n * T * (1.0 + 0.4 * y) / mu;
+    S.nf[NF_NU][j] = chi * n * T * (1.0 + 0.4 * y) / mu;
     const double Pr = (2.0 / 3.0) * (1.0 + 0.6 * y) * (1.0 + 0.8 * y + c12 * y * y) /
                       ((1.0 + 0.4 * y) * (1.0 + 1.2 * y + c32 * y * y));
-    S.nf[NF_N][j] = n;
-    S.nf[NF_U][j] = u;
-    S.nf[NF_T][j] = T;
-    S.nf[NF_NU][j] = nu;
-    S.nf[NF_S][j] = (1.0 - Pr) * q / (5.0 * n * T * T);
+    S.nf[NF_S][j] = (1.0 - Pr) * qj / (5.0 * n * T * T);
     S.nf[NF_PRE][j] = -bn * chi;
-    S.nf[NF_A][j] = Ag;
-    S.nf[NF_B][j] = Bg;
-    S.nf[NF_U1][j] = Ug;
-    S.nf[NF_FX][j] = Fx;
   }
   __syncthreads();
 
   // ---- 4. update -----------------------------------------------------------
-  const int j = tid & 63;
-  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int kbase = wv * VPT;
-  const bool valid = (i0 + j) < nsys;
-  const long long gnode = off + i0 + j;
+  const double* meq = SH::UNIFORM ? P.meq : S.tab;
+  const double* dpm = SH::UNIFORM ? P.dpm : S.tab + Q * Q;
+  const double* vel = SH::UNIFORM ? P.vel : S.tab + 2 * Q * Q;
   double pm[6] = {0, 0, 0, 0, 0, 0};
   {
-    const double n = S.nf[NF_N][j], u = S.nf[NF_U][j], T = S.nf[NF_T][j];
+    const double u = S.nf[NF_U][j], T = S.nf[NF_T][j];
     const double nu = S.nf[NF_NU][j], sS = S.nf[NF_S][j], pre = S.nf[NF_PRE][j];
     const double Ag = S.nf[NF_A][j], Bg = S.nf[NF_B][j], Ug = S.nf[NF_U1][j];
     const double Fx = S.nf[NF_FX][j];
     const double invT = 1.0 / T;
-
-    // Hermite equilibrium E_k = sum_l meq[k][l] a_l with
-    // a_0 = n, a_1 = n u, a_{l+1} = u a_l + l (T - 1) a_{l-1}
+    // Hermite equilibrium E_k = sum_l meq[k][l] a_l
     double E[VPT];
-    {
-      double am = n, a = n * u;
 #pragma unroll
-      for (int v = 0; v < VPT; ++v) E[v] = P.meq[(kbase + v) * Q] * am + P.meq[(kbase + v) * Q + 1] * a;
-      const double tm1 = T - 1.0;
+    for (int v = 0; v < VPT; ++v) E[v] = 0.0;
 #pragma unroll
-      for (int l = 1; l < Q - 1; ++l) {
-        const double an = u * a + (double)l * tm1 * am;
-        am = a;
-        a = an;
+    for (int l = 0; l < Q; ++l) {
+      const double al = S.a[l][j];
 #pragma unroll
-        for (int v = 0; v < VPT; ++v) E[v] += P.meq[(kbase + v) * Q + l + 1] * a;
-      }
+      for (int v = 0; v < VPT; ++v) E[v] += meq[(kbase + v) * Q + l] * al;
     }
     // momentum derivative (Dp F)_k, (Dp G)_k
     double dF[VPT], dG[VPT];
@@ -258,7 +331,7 @@ __device__ void stage_tile(const DevParams& P, const StageArgs& A, int tile, Sme
         const double gk = S.f[Q + kp][j + HF];
 #pragma unroll
         for (int v = 0; v < VPT; ++v) {
-          const double d = P.dpm[(kbase + v) * Q + kp];
+          const double d = dpm[(kbase + v) * Q + kp];
           dF[v] += d * fk;
           dG[v] += d * gk;
         }
@@ -267,7 +340,7 @@ __device__ void stage_tile(const DevParams& P, const StageArgs& A, int tile, Sme
 #pragma unroll
     for (int v = 0; v < VPT; ++v) {
       const int k = kbase + v;
-      const double pk = P.vel[k];
+      const double pk = vel[k];
       const double F = S.f[k][j + HF];
       const double G = S.f[Q + k][j + HF];
       const double xi = pk - u;
@@ -296,13 +369,10 @@ __device__ void stage_tile(const DevParams& P, const StageArgs& A, int tile, Sme
         Fo = LF;
         Go = LG;
       } else {
-        double Fn = F, Gn = G;
-        if (!A.first && valid) {
-          Fn = A.f_n[(long long)k * ntot + gnode];
-          Gn = A.f_n[(long long)(Q + k) * ntot + gnode];
-        }
-        Fo = A.alpha * Fn + A.beta * (F + P.dt * LF);
-        Go = A.alpha * Gn + A.beta * (G + P.dt * LG);
+        const double Fb = A.first ? F : Fn[v];
+        const double Gb = A.first ? G : Gn[v];
+        Fo = A.alpha * Fb + A.beta * (F + P.dt * LF);
+        Go = A.alpha * Gb + A.beta * (G + P.dt * LG);
       }
       if (valid) {
         A.f_out[(long long)k * ntot + gnode] = Fo;
@@ -317,84 +387,83 @@ __device__ void stage_tile(const DevParams& P, const StageArgs& A, int tile, Sme
       pm[5] += pk * Go;
     }
   }
-  if (A.rhs_mode) {
-    __syncthreads();
-    return;
-  }
   __syncthreads();  // faces (aliased by red) fully consumed
+  if (A.rhs_mode) return;
 #pragma unroll
-  for (int m = 0; m < 6; ++m) S.red[wv][m][j] = pm[m];
+  for (int m = 0; m < 6; ++m) S.red[g][m][j] = pm[m];
   __syncthreads();
 
   // ---- 5. moments of the new state --------------------------------------
-  if (tid < W && (i0 + tid) < nsys) {
-    double s[6];
+  for (int t = tid; t < 6 * W; t += NT) {
+    const int m = t / W, jj = t - m * W;
+    double s0 = 0.0, s1 = 0.0;
 #pragma unroll
-    for (int m = 0; m < 6; ++m) {
-      double acc = 0.0;
-#pragma unroll
-      for (int w = 0; w < NW; ++w) acc += S.red[w][m][tid];
-      s[m] = acc;
+    for (int gg = 0; gg + 1 < NG; gg += 2) {
+      s0 += S.red[gg][m][jj];
+      s1 += S.red[gg + 1][m][jj];
     }
-    const double n = s[0];
-    const double u = s[1] / n;
-    const double T = (2.0 / 3.0) * (0.5 * s[2] + s[4] - 0.5 * n * u * u) / n;
-    const double x3 = s[3] - 3.0 * u * s[2] + 3.0 * u * u * s[1] - u * u * u * s[0];
-    const double q = 0.5 * x3 + s[5] - u * s[4];
-    const long long g = off + i0 + tid;
-    A.mom_out[g] = n;
-    A.mom_out[ntot + g] = u;
-    A.mom_out[2 * ntot + g] = T;
-    A.mom_out[3 * ntot + g] = q;
+    if (NG & 1) s0 += S.red[NG - 1][m][jj];
+    S.msum[m][jj] = s0 + s1;
+  }
+  __syncthreads();
+  if (tid < W && valid) {
+    const double n = S.msum[0][tid];
+    const double u = S.msum[1][tid] / n;
+    const double T = (2.0 / 3.0) * (0.5 * S.msum[2][tid] + S.msum[4][tid] - 0.5 * n * u * u) / n;
+    const double x3 = S.msum[3][tid] - 3.0 * u * S.msum[2][tid] + 3.0 * u * u * S.msum[1][tid] - u * u * u * n;
+    const double q = 0.5 * x3 + S.msum[5][tid] - u * S.msum[4][tid];
+    A.mom_out[gnode] = n;
+    A.mom_out[ntot + gnode] = u;
+    A.mom_out[2 * ntot + gnode] = T;
+    A.mom_out[3 * ntot + gnode] = q;
     if (!(n > 0.0) || !(T > 0.0) || !isfinite(n) || !isfinite(T) || !isfinite(q) || !isfinite(u))
       P.status[0] = 1;
   }
   __syncthreads();
 }
 
-template <int Q, int NW>
-__global__ __launch_bounds__(64 * NW) void stage_kernel(DevParams P, StageArgs A) {
-  __shared__ Smem<Q, NW> S;
-  for (int t = blockIdx.x; t < P.ntiles; t += gridDim.x) stage_tile<Q, NW>(P, A, t, S);
+template <int Q, int W, int NG>
+__global__ __launch_bounds__(W * NG) void stage_kernel(DevParams P, StageArgs A) {
+  __shared__ Smem<Q, W, NG> S;
+  load_tables<Q, W, NG>(P, S);
+  for (int t = blockIdx.x; t < P.ntiles; t += gridDim.x) stage_tile<Q, W, NG>(P, A, t, S);
 }
 
 // Grid-wide barrier for the persistent kernel (all workgroups co-resident:
-// cooperative launch).  Agent-scope release/acquire makes the stage's global
-// writes of every XCD visible to all others.  The wait is bounded: on time-out
-// the abort latch is set and every workgroup leaves its step loop.
-__device__ bool grid_barrier(const DevParams& P, unsigned nblocks) {
+// cooperative launch).  A monotonically increasing arrival counter: barrier
+// number e completes when the counter reaches (e + 1) * nblocks.  An
+// agent-scope release fence before the arrival and an acquire fence after
+// the wait make each stage's global writes, from every XCD, visible to all
+// workgroups.  The wait is bounded: on time-out the abort latch is set and
+// every workgroup leaves its step loop.
+__device__ bool grid_barrier(const DevParams& P, unsigned nblocks, unsigned epoch) {
   __syncthreads();
-  __shared__ int s_abort;
+  __shared__ int s_ok;
   if (threadIdx.x == 0) {
-    unsigned* count = P.bar;
-    unsigned* gen = P.bar + 1;
-    const unsigned g = __hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __atomic_thread_fence(__ATOMIC_RELEASE);
-    const unsigned arrived = __hip_atomic_fetch_add(count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    int abort = 0;
-    if (arrived == nblocks - 1) {
-      __hip_atomic_store(count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_fetch_add(gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    } else {
-      long long spins = 0;
-      while (__hip_atomic_load(gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
-        __builtin_amdgcn_s_sleep(1);
-        if (++spins > (1ll << 22)) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __hip_atomic_fetch_add(P.bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned target = (epoch + 1u) * nblocks;
+    int ok = 1;
+    long long spins = 0;
+    while ((int)(__hip_atomic_load(P.bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) - target) < 0) {
+      __builtin_amdgcn_s_sleep(1);
+      if ((++spins & 1023) == 0) {
+        if (spins > (1ll << 24) ||
+            __hip_atomic_load(P.status + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
           __hip_atomic_store(P.status + 1, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          ok = 0;
           break;
         }
-        if (__hip_atomic_load(P.status + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
       }
     }
-    __atomic_thread_fence(__ATOMIC_ACQUIRE);
-    abort = __hip_atomic_load(P.status + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    s_abort = abort;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    s_ok = ok;
   }
   __syncthreads();
-  return s_abort == 0;
+  return s_ok != 0;
 }
 
-// Resets the barrier counters and the abort latch (a kernel rather than a
+// Resets the barrier counter and the abort latch (a kernel rather than a
 // memset so that the sequence stays valid under stream capture).
 __global__ void clear_barrier_kernel(DevParams P) {
   if (threadIdx.x == 0) {
@@ -413,11 +482,13 @@ struct PersistArgs {
   int nsteps;
 };
 
-template <int Q, int NW>
-__global__ __launch_bounds__(64 * NW) void persistent_kernel(DevParams P, PersistArgs R) {
-  __shared__ Smem<Q, NW> S;
+template <int Q, int W, int NG>
+__global__ __launch_bounds__(W * NG) void persistent_kernel(DevParams P, PersistArgs R) {
+  __shared__ Smem<Q, W, NG> S;
+  load_tables<Q, W, NG>(P, S);
   const double a_s[3] = {0.0, 0.75, 1.0 / 3.0};
   const double b_s[3] = {1.0, 0.25, 2.0 / 3.0};
+  unsigned epoch = 0;
   for (int step = 0; step < R.nsteps; ++step) {
     for (int s = 0; s < 3; ++s) {
       StageArgs A;
@@ -431,8 +502,8 @@ __global__ __launch_bounds__(64 * NW) void persistent_kernel(DevParams P, Persis
       A.beta = b_s[s];
       A.first = s == 0;
       A.rhs_mode = 0;
-      for (int t = blockIdx.x; t < P.ntiles; t += gridDim.x) stage_tile<Q, NW>(P, A, t, S);
-      if (!grid_barrier(P, gridDim.x)) return;
+      for (int t = blockIdx.x; t < P.ntiles; t += gridDim.x) stage_tile<Q, W, NG>(P, A, t, S);
+      if (!grid_barrier(P, gridDim.x, epoch++)) return;
     }
   }
 }
@@ -501,15 +572,18 @@ __global__ __launch_bounds__(256) void equilibrium_kernel(DevParams P, const dou
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+constexpr int WIDE = 64;    // tile width for large grids
+constexpr int NARROW = 16;  // tile width for grids too small to fill the chip
+
 struct Layout {
-  size_t tables, tiles, f1, f2, momA, momB, status, total;
+  size_t tables, tiles_wide, tiles_narrow, f1, f2, momA, momB, status, total;
   long long ntot;
-  int ntiles, ms, mf;
+  int ntiles_wide, ntiles_narrow, ms, mf;
 };
 
-int count_tiles(const evlb_params* p) {
+int count_tiles(const evlb_params* p, int w) {
   int t = 0;
-  for (int s = 0; s < p->n_sys; ++s) t += (p->nx[s] + W - 1) / W;
+  for (int s = 0; s < p->n_sys; ++s) t += (p->nx[s] + w - 1) / w;
   return t;
 }
 
@@ -541,6 +615,7 @@ int validate(const evlb_params* p) {
   if (p->term_mask & ~EVLB_TERM_ALL) return EVLB_EINVAL;
   if (!(p->weno_eps > 0) || !std::isfinite(p->g_ext)) return EVLB_EINVAL;
   if (p->exec_mode < 0 || p->exec_mode > 2) return EVLB_EINVAL;
+  if (p->tile_nodes != 0 && p->tile_nodes != WIDE && p->tile_nodes != NARROW) return EVLB_EINVAL;
   int ms, mf = 0;
   if (!is_even_multiple(p->sigma, p->dx, &ms) || ms > MS_MAX) return EVLB_EINVAL;
   if (p->force_model == EVLB_FORCE_EV1) {
@@ -557,15 +632,18 @@ Layout make_layout(const evlb_params* p) {
   Layout L{};
   L.ntot = 0;
   for (int s = 0; s < p->n_sys; ++s) L.ntot += p->nx[s];
-  L.ntiles = count_tiles(p);
+  L.ntiles_wide = count_tiles(p, WIDE);
+  L.ntiles_narrow = count_tiles(p, NARROW);
   L.ms = (int)llround(p->sigma / p->dx);
   L.mf = p->force_model == EVLB_FORCE_EV1 ? (int)llround(p->r_cut / p->dx) : 0;
   const int q = p->q;
   size_t off = 0;
   L.tables = off;
   off += align256(sizeof(double) * (size_t)(q + 2 * q * q + 2 * L.ms + 1 + (L.mf > 0 ? L.mf : 1)));
-  L.tiles = off;
-  off += align256(sizeof(int4) * (size_t)L.ntiles);
+  L.tiles_wide = off;
+  off += align256(sizeof(int4) * (size_t)L.ntiles_wide);
+  L.tiles_narrow = off;
+  off += align256(sizeof(int4) * (size_t)L.ntiles_narrow);
   const size_t fbytes = align256(sizeof(double) * 2 * (size_t)q * (size_t)L.ntot);
   L.f1 = off; off += fbytes;
   L.f2 = off; off += fbytes;
@@ -584,7 +662,7 @@ struct evlb_ctx {
   std::vector<int32_t> nx;
   std::vector<double> vel;
   Layout L;
-  DevParams dp;
+  DevParams dp;  // tiles/ntiles of the wide shape; launches patch them
   char* ws;
   int device;
   int cus;
@@ -597,19 +675,41 @@ namespace {
     if ((call) != hipSuccess) return EVLB_EHIP; \
   } while (0)
 
-template <int Q, int NW>
+// launch shapes per quadrature order: wide tiles (64 nodes, NG groups) and
+// narrow tiles (16 nodes, one velocity per thread)
+template <int Q> struct WideNG;
+template <> struct WideNG<8> { static constexpr int v = 4; };
+template <> struct WideNG<16> { static constexpr int v = 8; };
+template <> struct WideNG<24> { static constexpr int v = 8; };
+
+template <int W>
+DevParams params_for(const evlb_ctx* c) {
+  DevParams P = c->dp;
+  if (W == NARROW) {
+    P.tiles = (const int4*)(c->ws + c->L.tiles_narrow);
+    P.ntiles = c->L.ntiles_narrow;
+  } else {
+    P.tiles = (const int4*)(c->ws + c->L.tiles_wide);
+    P.ntiles = c->L.ntiles_wide;
+  }
+  return P;
+}
+
+template <int Q, int W, int NG>
 int launch_stage(evlb_ctx* c, const StageArgs& A, hipStream_t st) {
-  hipLaunchKernelGGL((stage_kernel<Q, NW>), dim3(c->L.ntiles), dim3(64 * NW), 0, st, c->dp, A);
+  const DevParams P = params_for<W>(c);
+  hipLaunchKernelGGL((stage_kernel<Q, W, NG>), dim3(P.ntiles), dim3(W * NG), 0, st, P, A);
   return hipGetLastError() == hipSuccess ? EVLB_OK : EVLB_EHIP;
 }
 
-template <int Q, int NW>
+template <int Q, int W, int NG>
 int launch_persistent(evlb_ctx* c, double* f, int nsteps, hipStream_t st) {
   int per_cu = 0;
-  EVLB_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, persistent_kernel<Q, NW>, 64 * NW, 0));
+  EVLB_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, persistent_kernel<Q, W, NG>, W * NG, 0));
   if (per_cu < 1) return EVLB_EHIP;
+  DevParams P = params_for<W>(c);
   int grid = per_cu * c->cus;
-  if (grid > c->L.ntiles) grid = c->L.ntiles;
+  if (grid > P.ntiles) grid = P.ntiles;
   PersistArgs R;
   R.f = f;
   R.f1 = (double*)(c->ws + c->L.f1);
@@ -617,23 +717,13 @@ int launch_persistent(evlb_ctx* c, double* f, int nsteps, hipStream_t st) {
   R.momA = (double*)(c->ws + c->L.momA);
   R.momB = (double*)(c->ws + c->L.momB);
   R.nsteps = nsteps;
-  hipLaunchKernelGGL(clear_barrier_kernel, dim3(1), dim3(64), 0, st, c->dp);
+  hipLaunchKernelGGL(clear_barrier_kernel, dim3(1), dim3(64), 0, st, P);
   EVLB_HIP(hipGetLastError());
-  DevParams P = c->dp;
   void* args[] = {&P, &R};
-  EVLB_HIP(hipLaunchCooperativeKernel((const void*)persistent_kernel<Q, NW>, dim3(grid), dim3(64 * NW), args, 0,
+  EVLB_HIP(hipLaunchCooperativeKernel((const void*)persistent_kernel<Q, W, NG>, dim3(grid), dim3(W * NG), args, 0,
                                       st));
   return EVLB_OK;
 }
-
-template <int Q>
-struct QCfg;
-template <>
-struct QCfg<8> { static constexpr int NW = 4; };
-template <>
-struct QCfg<16> { static constexpr int NW = 8; };
-template <>
-struct QCfg<24> { static constexpr int NW = 8; };
 
 template <int Q>
 int run_moments(evlb_ctx* c, const double* f, double* n, double* u, double* T, double* q, hipStream_t st) {
@@ -643,17 +733,22 @@ int run_moments(evlb_ctx* c, const double* f, double* n, double* u, double* T, d
   return hipGetLastError() == hipSuccess ? EVLB_OK : EVLB_EHIP;
 }
 
-template <int Q>
-int run_step(evlb_ctx* c, double* f, int nsteps, hipStream_t st) {
-  constexpr int NW = QCfg<Q>::NW;
+// tile width: explicit, or narrow when wide tiles cannot occupy every CU twice
+int pick_width(const evlb_ctx* c) {
+  if (c->p.tile_nodes) return c->p.tile_nodes;
+  return c->L.ntiles_wide >= 4 * c->cus ? WIDE : NARROW;
+}
+
+template <int Q, int W, int NG>
+int run_step_shape(evlb_ctx* c, double* f, int nsteps, hipStream_t st) {
   const long long nt = c->L.ntot;
   double* momA = (double*)(c->ws + c->L.momA);
   double* momB = (double*)(c->ws + c->L.momB);
   int rc = run_moments<Q>(c, f, momA, momA + nt, momA + 2 * nt, momA + 3 * nt, st);
   if (rc) return rc;
   int mode = c->p.exec_mode;
-  if (mode == EVLB_EXEC_AUTO) mode = (c->L.ntiles <= 2 * c->cus) ? EVLB_EXEC_PERSISTENT : EVLB_EXEC_PER_STAGE;
-  if (mode == EVLB_EXEC_PERSISTENT) return launch_persistent<Q, NW>(c, f, nsteps, st);
+  if (mode == EVLB_EXEC_AUTO) mode = EVLB_EXEC_PER_STAGE;
+  if (mode == EVLB_EXEC_PERSISTENT) return launch_persistent<Q, W, NG>(c, f, nsteps, st);
   double* f1 = (double*)(c->ws + c->L.f1);
   double* f2 = (double*)(c->ws + c->L.f2);
   const double a_s[3] = {0.0, 0.75, 1.0 / 3.0};
@@ -671,7 +766,7 @@ int run_step(evlb_ctx* c, double* f, int nsteps, hipStream_t st) {
       A.beta = b_s[s];
       A.first = s == 0;
       A.rhs_mode = 0;
-      rc = launch_stage<Q, NW>(c, A, st);
+      rc = launch_stage<Q, W, NG>(c, A, st);
       if (rc) return rc;
     }
   }
@@ -679,8 +774,13 @@ int run_step(evlb_ctx* c, double* f, int nsteps, hipStream_t st) {
 }
 
 template <int Q>
-int run_rhs(evlb_ctx* c, const double* f, double* L, hipStream_t st) {
-  constexpr int NW = QCfg<Q>::NW;
+int run_step(evlb_ctx* c, double* f, int nsteps, hipStream_t st) {
+  if (pick_width(c) == NARROW) return run_step_shape<Q, NARROW, Q>(c, f, nsteps, st);
+  return run_step_shape<Q, WIDE, WideNG<Q>::v>(c, f, nsteps, st);
+}
+
+template <int Q, int W, int NG>
+int run_rhs_shape(evlb_ctx* c, const double* f, double* L, hipStream_t st) {
   const long long nt = c->L.ntot;
   double* momA = (double*)(c->ws + c->L.momA);
   double* momB = (double*)(c->ws + c->L.momB);
@@ -696,7 +796,13 @@ int run_rhs(evlb_ctx* c, const double* f, double* L, hipStream_t st) {
   A.beta = 1.0;
   A.first = 1;
   A.rhs_mode = 1;
-  return launch_stage<Q, NW>(c, A, st);
+  return launch_stage<Q, W, NG>(c, A, st);
+}
+
+template <int Q>
+int run_rhs(evlb_ctx* c, const double* f, double* L, hipStream_t st) {
+  if (pick_width(c) == NARROW) return run_rhs_shape<Q, NARROW, Q>(c, f, L, st);
+  return run_rhs_shape<Q, WIDE, WideNG<Q>::v>(c, f, L, st);
 }
 
 template <int Q>
@@ -761,18 +867,19 @@ int evlb_init(const evlb_params* params, void* d_workspace, size_t ws_bytes, voi
   host.insert(host.end(), t.dpm.begin(), t.dpm.end());
   host.insert(host.end(), t.savg.begin(), t.savg.end());
   host.insert(host.end(), t.cfor.begin(), t.cfor.end());
-  std::vector<int4> tiles;
-  tiles.reserve(L.ntiles);
+  std::vector<int4> tw, tn;
   int off = 0;
   for (int s = 0; s < params->n_sys; ++s) {
-    for (int i0 = 0; i0 < params->nx[s]; i0 += W) tiles.push_back(make_int4(off, params->nx[s], i0, 0));
+    for (int i0 = 0; i0 < params->nx[s]; i0 += WIDE) tw.push_back(make_int4(off, params->nx[s], i0, 0));
+    for (int i0 = 0; i0 < params->nx[s]; i0 += NARROW) tn.push_back(make_int4(off, params->nx[s], i0, 0));
     off += params->nx[s];
   }
   hipStream_t st = (hipStream_t)hip_stream;
   double* tab = (double*)(c->ws + L.tables);
   // synchronous copies: the host vectors die when this call returns
   if (hipMemcpy(tab, host.data(), host.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemcpy(c->ws + L.tiles, tiles.data(), tiles.size() * sizeof(int4), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(c->ws + L.tiles_wide, tw.data(), tw.size() * sizeof(int4), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(c->ws + L.tiles_narrow, tn.data(), tn.size() * sizeof(int4), hipMemcpyHostToDevice) != hipSuccess ||
       hipMemset(c->ws + L.status, 0, 256) != hipSuccess) {
     delete c;
     return EVLB_EHIP;
@@ -784,8 +891,8 @@ int evlb_init(const evlb_params* params, void* d_workspace, size_t ws_bytes, voi
   d.dpm = tab + q + q * q;
   d.savg = tab + q + 2 * q * q;
   d.cfor = tab + q + 2 * q * q + 2 * L.ms + 1;
-  d.tiles = (const int4*)(c->ws + L.tiles);
-  d.ntiles = L.ntiles;
+  d.tiles = (const int4*)(c->ws + L.tiles_wide);
+  d.ntiles = L.ntiles_wide;
   d.ms = L.ms;
   d.mf = L.mf;
   d.hn = L.mf > L.ms + 2 ? L.mf : L.ms + 2;

@@ -39,6 +39,7 @@ class evlb_params(ctypes.Structure):
         ("weno_eps", ctypes.c_double),
         ("g_ext", ctypes.c_double),
         ("exec_mode", ctypes.c_int32),
+        ("tile_nodes", ctypes.c_int32),
     ]
 
 
@@ -93,14 +94,14 @@ def _check(code, what):
 
 def make_params(q, dx, dt, nx, sigma=1.0, phi_sigma=1.0, gamma=6.0, r_cut=5.0,
                 force_model=EVLB_FORCE_EV1, term_mask=EVLB_TERM_ALL, weno_eps=1e-6,
-                g_ext=0.0, exec_mode=EVLB_EXEC_AUTO):
+                g_ext=0.0, exec_mode=EVLB_EXEC_AUTO, tile_nodes=0):
     """evlb_params for one or several periodic 1D systems (nx: int or list).
     The returned structure keeps its nx array alive."""
     nxs = [int(nx)] if isinstance(nx, (int,)) else [int(v) for v in nx]
     arr = (ctypes.c_int32 * len(nxs))(*nxs)
     p = evlb_params(EVLB_ABI_VERSION, 1, len(nxs), arr, int(q), float(dx), float(dt), float(sigma),
                     float(phi_sigma), float(gamma), float(r_cut), int(force_model), int(term_mask),
-                    float(weno_eps), float(g_ext), int(exec_mode))
+                    float(weno_eps), float(g_ext), int(exec_mode), int(tile_nodes))
     p._nx_keepalive = arr
     return p
 
@@ -189,9 +190,12 @@ class Solver:
 
     def __del__(self):
         ctx = getattr(self, "ctx", None)
-        if ctx:
-            evlb_destroy(ctx)
-            self.ctx = None
+        if ctx and _lib is not None and getattr(_lib, "evlb_destroy", None) is not None:
+            try:
+                _lib.evlb_destroy(ctx)
+            except Exception:  # interpreter shutdown
+                pass
+        self.ctx = None
 
     def new_state(self):
         return torch.empty((2, self.q, self.n_tot), dtype=torch.float64, device=self.device)

@@ -78,26 +78,28 @@ def test_equilibrium_and_moments_match_oracle():
             assert np.max(np.abs(mom[i] - ref[i])) <= 1e-13 * np.max(np.abs(ref[i])) + 1e-16, i
 
 
+@pytest.mark.parametrize("tile", [16, 64])
 @pytest.mark.parametrize("mask", [1, 2, 4, 8, 15])
 @pytest.mark.parametrize("which", ["phase", "slab"])
-def test_rhs_matches_oracle_per_term(mask, which):
+def test_rhs_matches_oracle_per_term(mask, which, tile):
     c, n, u, T = case_phase() if which == "phase" else case_slab()
-    print(f"rhs case {which} mask={mask}", flush=True)
+    print(f"rhs case {which} mask={mask} tile={tile}", flush=True)
     tb = oracle_tables(c, term_mask=mask)
     F, G = nonequilibrium(*step1d.initial_state(n, u + 0.02 * np.sin(np.arange(len(n)) / 7.0), T, tb), tb)
     LF, LG = step1d.rhs(F, G, tb)
-    s = solver(c, term_mask=mask)
+    s = solver(c, term_mask=mask, tile_nodes=tile)
     L = s.rhs(td(np.stack([F, G]))).cpu().numpy()
     assert rel(L, [LF, LG]) < 1e-11
 
 
+@pytest.mark.parametrize("tile", [16, 64])
 @pytest.mark.parametrize("mode", [1, 2])
-def test_one_and_ten_steps_match_oracle(mode):
+def test_one_and_ten_steps_match_oracle(mode, tile):
     for c, n, u, T in (case_phase(), case_slab()):
-        print(f"steps case Q={c['Q']} nx={c['nx']} mode={mode}", flush=True)
+        print(f"steps case Q={c['Q']} nx={c['nx']} mode={mode} tile={tile}", flush=True)
         tb = oracle_tables(c)
         F, G = step1d.initial_state(n, u, T, tb)
-        s = solver(c, exec_mode=mode)
+        s = solver(c, exec_mode=mode, tile_nodes=tile)
         f = s.equilibrium(td(n), td(u), td(T))
         s.step(f, 1)
         F1, G1 = step1d.rk3_step(F, G, tb)
@@ -126,13 +128,14 @@ def test_phase_separation_1000_steps_match_oracle():
 def test_exec_modes_agree_and_repeat_bitwise():
     c, n, u, T = case_slab(2048)
     out = []
-    for mode in (1, 2, 1):
-        s = solver(c, exec_mode=mode)
+    for mode, tile in ((1, 64), (2, 64), (1, 64), (1, 16), (2, 16)):
+        s = solver(c, exec_mode=mode, tile_nodes=tile)
         f = s.equilibrium(td(n), td(u), td(T))
         s.step(f, 20)
         out.append(f.cpu().numpy())
     assert np.array_equal(out[0], out[2])
-    assert rel(out[1], out[0]) < 1e-14
+    for o in out[1:]:
+        assert rel(o, out[0]) < 1e-14
 
 
 def test_ragged_batch_matches_independent_oracle_runs():
@@ -143,8 +146,8 @@ def test_ragged_batch_matches_independent_oracle_runs():
     n = np.concatenate([s[0] for s in systems])
     u = np.concatenate([s[1] for s in systems])
     T = np.concatenate([s[2] for s in systems])
-    for mode in (1, 2):
-        s = solver(c, nx=nxs, exec_mode=mode)
+    for mode, tile in ((1, 64), (2, 64), (1, 16), (2, 16)):
+        s = solver(c, nx=nxs, exec_mode=mode, tile_nodes=tile)
         f = s.equilibrium(td(n), td(u), td(T))
         s.step(f, 5)
         got = f.cpu().numpy()
