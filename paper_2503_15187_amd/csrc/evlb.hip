@@ -429,6 +429,243 @@ __global__ __launch_bounds__(W * NG) void stage_kernel(DevParams P, StageArgs A)
   for (int t = blockIdx.x; t < P.ntiles; t += gridDim.x) stage_tile<Q, W, NG>(P, A, t, S);
 }
 
+// ---------------------------------------------------------------------------
+// Column shape: one wavefront per tile of WC = 63 nodes, thread = node.  Each
+// thread keeps its node's F, G columns and Hermite moments in registers, so
+// the q x q contractions (equilibrium, momentum derivative) need no LDS
+// traffic and the velocity moments of the new state are a per-thread sum.
+// The 64 lanes compute the 64 WENO-5 faces of a row (face j between nodes
+// j-1 and j); a node's right face comes from the next lane by a shuffle.
+// ---------------------------------------------------------------------------
+constexpr int WC = 63;
+
+template <int Q>
+struct SmemCol {
+  double f[2 * Q][WC + 2 * HF + 1];  // columns: node i0 - 3 + c, c = 0..68
+  double n[WC + 2 * HN_MAX];
+  double u[WC + 4], T[WC + 4], X[WC + 4], chi[WC + 4];
+};
+
+template <int Q>
+__device__ void stage_tile_col(const DevParams& P, const StageArgs& A, int tile, SmemCol<Q>& S,
+                               const double* __restrict__ vel, const double* __restrict__ meq,
+                               const double* __restrict__ dpm) {
+  const int lane = threadIdx.x;  // 0..63
+  const int4 td = P.tiles[tile];
+  const int off = td.x, nsys = td.y, i0 = td.z;
+  const long long ntot = P.ntot;
+  const int hn = P.hn;
+  const bool valid = lane < WC && (i0 + lane) < nsys;
+  const long long gnode = off + i0 + lane;
+
+  // ---- 1. load: own column to registers and LDS, halo columns to LDS ----
+  double Fc[Q], Gc[Q];
+  {
+    const long long gown = off + wrapi(i0 + lane, nsys);  // lane 63: right halo node 63
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+      Fc[k] = A.f_prev[(long long)k * ntot + gown];
+      Gc[k] = A.f_prev[(long long)(Q + k) * ntot + gown];
+    }
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+      S.f[k][lane + HF] = Fc[k];
+      S.f[Q + k][lane + HF] = Gc[k];
+    }
+    if (lane < 5) {  // columns 0, 1, 2 (nodes -3..-1) and 67, 68 (nodes 64, 65)
+      const int c = lane < 3 ? lane : lane + 64;
+      const long long gh = off + wrapi(i0 - HF + c, nsys);
+#pragma unroll
+      for (int r = 0; r < 2 * Q; ++r) S.f[r][c] = A.f_prev[(long long)r * ntot + gh];
+    }
+  }
+  const double* mn = A.mom_in;
+  for (int c = lane; c < WC + 2 * hn; c += 64) S.n[c] = mn[off + wrapi(i0 - hn + c, nsys)];
+  for (int c = lane; c < WC + 4; c += 64) {
+    const int node = off + wrapi(i0 - 2 + c, nsys);
+    S.u[c] = mn[ntot + node];
+    S.T[c] = mn[2 * ntot + node];
+  }
+  const double qj = valid ? mn[3 * ntot + gnode] : 0.0;
+  __syncthreads();
+
+  // ---- 2. contact value and X = n^2 chi T on nodes -2..64 ---------------
+  for (int c = lane; c < WC + 4; c += 64) {
+    const int cn = c + hn - 2;
+    double s0 = 0.0, s1 = 0.0;
+    int jj = -P.ms;
+    for (; jj + 1 <= P.ms; jj += 2) {
+      s0 += P.savg[jj + P.ms] * S.n[cn + jj];
+      s1 += P.savg[jj + 1 + P.ms] * S.n[cn + jj + 1];
+    }
+    if (jj <= P.ms) s0 += P.savg[jj + P.ms] * S.n[cn + jj];
+    const double eta = P.eta_c * (s0 + s1);
+    const double om = 1.0 - eta;
+    const double chi = (2.0 - eta) / (2.0 * om * om * om);
+    const double nn = S.n[cn];
+    S.chi[c] = chi;
+    S.X[c] = nn * nn * chi * S.T[c];
+  }
+  __syncthreads();
+
+  // ---- 3. node fields of the own node -------------------------------------
+  const int jw = lane < WC ? lane : WC - 1;  // lane 63 mirrors lane 62 (no node)
+  const int c = jw + 2, cn = jw + hn;
+  const double n = S.n[cn], u = S.u[c], T = S.T[c], chi = S.chi[c];
+  const double idx12 = P.inv_dx * (1.0 / 12.0);
+  double Fx = P.g_ext;
+  if (P.force_model == EVLB_FORCE_EV1) {
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    int m = 1;
+    for (; m + 3 <= P.mf; m += 4) {
+      s0 += P.cfor[m - 1] * (S.n[cn + m] - S.n[cn - m]);
+      s1 += P.cfor[m] * (S.n[cn + m + 1] - S.n[cn - m - 1]);
+      s2 += P.cfor[m + 1] * (S.n[cn + m + 2] - S.n[cn - m - 2]);
+      s3 += P.cfor[m + 2] * (S.n[cn + m + 3] - S.n[cn - m - 3]);
+    }
+    for (; m <= P.mf; ++m) s0 += P.cfor[m - 1] * (S.n[cn + m] - S.n[cn - m]);
+    Fx += (s0 + s1) + (s2 + s3);
+  } else if (P.force_model == EVLB_FORCE_EV2) {
+    const double d1 = (S.n[cn - 2] - 8.0 * S.n[cn - 1] + 8.0 * S.n[cn + 1] - S.n[cn + 2]) * idx12;
+    const double d3 = (-S.n[cn - 2] + 2.0 * S.n[cn - 1] - 2.0 * S.n[cn + 1] + S.n[cn + 2]) *
+                      (0.5 * P.inv_dx * P.inv_dx * P.inv_dx);
+    Fx += P.two_a * d1 + P.kappa * d3;
+  }
+  const double Ag = (S.X[c - 2] - 8.0 * S.X[c - 1] + 8.0 * S.X[c + 1] - S.X[c + 2]) * idx12 / S.X[c];
+  const double Bg = (S.T[c - 2] - 8.0 * S.T[c - 1] + 8.0 * S.T[c + 1] - S.T[c + 2]) * idx12 / T;
+  const double Ug = (S.u[c - 2] - 8.0 * S.u[c - 1] + 8.0 * S.u[c + 1] - S.u[c + 2]) * idx12;
+  const double bn = P.b * n;
+  const double y = bn * chi;
+  const double c12 = 0.16 * (1.0 + 12.0 / M_PI);
+  const double c32 = 0.36 * (1.0 + 32.0 / (9.0 * M_PI));
+  const double mu = P.mu0c * sqrt(T) * (1.0 / chi + 0.8 * bn + c12 * bn * bn * chi);
+  const double nu = chi * n * T * (1.0 + 0.4 * y) / mu;
+  const double Pr = (2.0 / 3.0) * (1.0 + 0.6 * y) * (1.0 + 0.8 * y + c12 * y * y) /
+                    ((1.0 + 0.4 * y) * (1.0 + 1.2 * y + c32 * y * y));
+  const double sS = (1.0 - Pr) * qj / (5.0 * n * T * T);
+  const double pre = -bn * chi;
+  const double invT = 1.0 / T;
+  // Hermite moments a_0 = n, a_1 = n u, a_{l+1} = u a_l + l (T - 1) a_{l-1}
+  double a[Q];
+  a[0] = n;
+  a[1] = n * u;
+#pragma unroll
+  for (int l = 1; l < Q - 1; ++l) a[l + 1] = u * a[l] + (double)l * (T - 1.0) * a[l - 1];
+
+  // ---- 4. update, velocity by velocity -----------------------------------
+  double pm[6] = {0, 0, 0, 0, 0, 0};
+  const bool adv = P.term_mask & EVLB_TERM_ADV;
+  const bool frc = P.term_mask & EVLB_TERM_FORCE;
+  const bool j0 = P.term_mask & EVLB_TERM_J0;
+  const bool j1 = P.term_mask & EVLB_TERM_J1;
+#pragma unroll 1
+  for (int k = 0; k < Q; ++k) {
+    double Fb = 0.0, Gb = 0.0;
+    if (!A.first && !A.rhs_mode && valid) {
+      Fb = A.f_n[(long long)k * ntot + gnode];
+      Gb = A.f_n[(long long)(Q + k) * ntot + gnode];
+    }
+    const double pk = vel[k];
+    double LF = 0.0, LG = 0.0;
+    if (adv) {
+      // face `lane` of rows k (F) and Q + k (G); upwind by the sign of p_k
+      const bool pos = k >= Q / 2;
+      const int b0 = pos ? lane : lane + 5;
+      const int st = pos ? 1 : -1;
+      const double* fr = &S.f[k][0];
+      const double* gr = &S.f[Q + k][0];
+      const double hF = weno5(fr[b0], fr[b0 + st], fr[b0 + 2 * st], fr[b0 + 3 * st], fr[b0 + 4 * st], P.weno_eps);
+      const double hG = weno5(gr[b0], gr[b0 + st], gr[b0 + 2 * st], gr[b0 + 3 * st], gr[b0 + 4 * st], P.weno_eps);
+      const double hFr = __shfl_down(hF, 1);
+      const double hGr = __shfl_down(hG, 1);
+      LF = -pk * (hFr - hF) * P.inv_dx;
+      LG = -pk * (hGr - hG) * P.inv_dx;
+    }
+    double E0 = 0.0, E1 = 0.0;
+    const double* mrow = meq + k * Q;
+#pragma unroll
+    for (int l = 0; l < Q; l += 2) {
+      E0 += mrow[l] * a[l];
+      E1 += mrow[l + 1] * a[l + 1];
+    }
+    const double E = E0 + E1;
+    const double Fk = S.f[k][lane + HF];
+    const double Gk = S.f[Q + k][lane + HF];
+    if (frc) {
+      const double* drow = dpm + k * Q;
+      double dF0 = 0.0, dF1 = 0.0, dG0 = 0.0, dG1 = 0.0;
+#pragma unroll
+      for (int kk = 0; kk < Q; kk += 2) {
+        dF0 += drow[kk] * Fc[kk];
+        dF1 += drow[kk + 1] * Fc[kk + 1];
+        dG0 += drow[kk] * Gc[kk];
+        dG1 += drow[kk + 1] * Gc[kk + 1];
+      }
+      LF -= Fx * (dF0 + dF1);
+      LG -= Fx * (dG0 + dG1);
+    }
+    const double xi = pk - u;
+    const double th = xi * xi * invT;
+    if (j0) {
+      const double FS = E * (1.0 + sS * xi * (th - 3.0));
+      const double GS = T * E * (1.0 + sS * xi * (th - 1.0));
+      LF -= nu * (Fk - FS);
+      LG -= nu * (Gk - GS);
+    }
+    if (j1) {
+      LF += pre * E * (xi * (Ag + 0.3 * (th - 3.0) * Bg) + 0.6 * (th - 1.0) * Ug);
+      LG += pre * T * E * (xi * (Ag + 0.3 * (th - 1.0) * Bg) + 0.2 * (3.0 * th - 1.0) * Ug);
+    }
+    double Fo, Go;
+    if (A.rhs_mode) {
+      Fo = LF;
+      Go = LG;
+    } else {
+      if (A.first) {
+        Fb = Fk;
+        Gb = Gk;
+      }
+      Fo = A.alpha * Fb + A.beta * (Fk + P.dt * LF);
+      Go = A.alpha * Gb + A.beta * (Gk + P.dt * LG);
+    }
+    if (valid) {
+      A.f_out[(long long)k * ntot + gnode] = Fo;
+      A.f_out[(long long)(Q + k) * ntot + gnode] = Go;
+    }
+    const double p2 = pk * pk;
+    pm[0] += Fo;
+    pm[1] += pk * Fo;
+    pm[2] += p2 * Fo;
+    pm[3] += p2 * pk * Fo;
+    pm[4] += Go;
+    pm[5] += pk * Go;
+  }
+
+  // ---- 5. moments of the new state ----------------------------------------
+  if (!A.rhs_mode && valid) {
+    const double n1 = pm[0];
+    const double u1 = pm[1] / n1;
+    const double T1 = (2.0 / 3.0) * (0.5 * pm[2] + pm[4] - 0.5 * n1 * u1 * u1) / n1;
+    const double x3 = pm[3] - 3.0 * u1 * pm[2] + 3.0 * u1 * u1 * pm[1] - u1 * u1 * u1 * n1;
+    const double q1 = 0.5 * x3 + pm[5] - u1 * pm[4];
+    A.mom_out[gnode] = n1;
+    A.mom_out[ntot + gnode] = u1;
+    A.mom_out[2 * ntot + gnode] = T1;
+    A.mom_out[3 * ntot + gnode] = q1;
+    if (!(n1 > 0.0) || !(T1 > 0.0) || !isfinite(n1) || !isfinite(T1) || !isfinite(q1) || !isfinite(u1))
+      P.status[0] = 1;
+  }
+  __syncthreads();
+}
+
+template <int Q>
+__global__ __launch_bounds__(64) void stage_kernel_col(DevParams P, StageArgs A, const double* __restrict__ vel,
+                                                       const double* __restrict__ meq,
+                                                       const double* __restrict__ dpm) {
+  __shared__ SmemCol<Q> S;
+  for (int t = blockIdx.x; t < P.ntiles; t += gridDim.x) stage_tile_col<Q>(P, A, t, S, vel, meq, dpm);
+}
+
 // Grid-wide barrier for the persistent kernel (all workgroups co-resident:
 // cooperative launch).  A monotonically increasing arrival counter: barrier
 // number e completes when the counter reaches (e + 1) * nblocks.  An
@@ -482,10 +719,38 @@ struct PersistArgs {
   int nsteps;
 };
 
+// Persistent kernel: all stages of nsteps steps in one cooperative launch,
+// workgroups separated by grid barriers between stages.
 template <int Q, int W, int NG>
-__global__ __launch_bounds__(W * NG) void persistent_kernel(DevParams P, PersistArgs R) {
-  __shared__ Smem<Q, W, NG> S;
-  load_tables<Q, W, NG>(P, S);
+struct GroupShape {
+  static constexpr int NT = W * NG;
+  typedef Smem<Q, W, NG> Shared;
+  __device__ static void prologue(const DevParams& P, Shared& S) { load_tables<Q, W, NG>(P, S); }
+  __device__ static void tile(const DevParams& P, const StageArgs& A, int t, Shared& S, const double*,
+                              const double*, const double*) {
+    stage_tile<Q, W, NG>(P, A, t, S);
+  }
+};
+
+template <int Q>
+struct ColumnShape {
+  static constexpr int NT = 64;
+  typedef SmemCol<Q> Shared;
+  __device__ static void prologue(const DevParams&, Shared&) {}
+  __device__ static void tile(const DevParams& P, const StageArgs& A, int t, Shared& S,
+                              const double* __restrict__ vel, const double* __restrict__ meq,
+                              const double* __restrict__ dpm) {
+    stage_tile_col<Q>(P, A, t, S, vel, meq, dpm);
+  }
+};
+
+template <class SHAPE>
+__global__ __launch_bounds__(SHAPE::NT) void persistent_kernel(DevParams P, PersistArgs R,
+                                                               const double* __restrict__ vel,
+                                                               const double* __restrict__ meq,
+                                                               const double* __restrict__ dpm) {
+  __shared__ typename SHAPE::Shared S;
+  SHAPE::prologue(P, S);
   const double a_s[3] = {0.0, 0.75, 1.0 / 3.0};
   const double b_s[3] = {1.0, 0.25, 2.0 / 3.0};
   unsigned epoch = 0;
@@ -502,7 +767,7 @@ __global__ __launch_bounds__(W * NG) void persistent_kernel(DevParams P, Persist
       A.beta = b_s[s];
       A.first = s == 0;
       A.rhs_mode = 0;
-      for (int t = blockIdx.x; t < P.ntiles; t += gridDim.x) stage_tile<Q, W, NG>(P, A, t, S);
+      for (int t = blockIdx.x; t < P.ntiles; t += gridDim.x) SHAPE::tile(P, A, t, S, vel, meq, dpm);
       if (!grid_barrier(P, gridDim.x, epoch++)) return;
     }
   }
@@ -576,9 +841,9 @@ constexpr int WIDE = 64;    // tile width for large grids
 constexpr int NARROW = 16;  // tile width for grids too small to fill the chip
 
 struct Layout {
-  size_t tables, tiles_wide, tiles_narrow, f1, f2, momA, momB, status, total;
+  size_t tables, tiles_wide, tiles_narrow, tiles_col, f1, f2, momA, momB, status, total;
   long long ntot;
-  int ntiles_wide, ntiles_narrow, ms, mf;
+  int ntiles_wide, ntiles_narrow, ntiles_col, ms, mf;
 };
 
 int count_tiles(const evlb_params* p, int w) {
@@ -615,7 +880,8 @@ int validate(const evlb_params* p) {
   if (p->term_mask & ~EVLB_TERM_ALL) return EVLB_EINVAL;
   if (!(p->weno_eps > 0) || !std::isfinite(p->g_ext)) return EVLB_EINVAL;
   if (p->exec_mode < 0 || p->exec_mode > 2) return EVLB_EINVAL;
-  if (p->tile_nodes != 0 && p->tile_nodes != WIDE && p->tile_nodes != NARROW) return EVLB_EINVAL;
+  if (p->tile_nodes != 0 && p->tile_nodes != WIDE && p->tile_nodes != NARROW && p->tile_nodes != WC)
+    return EVLB_EINVAL;
   int ms, mf = 0;
   if (!is_even_multiple(p->sigma, p->dx, &ms) || ms > MS_MAX) return EVLB_EINVAL;
   if (p->force_model == EVLB_FORCE_EV1) {
@@ -634,6 +900,7 @@ Layout make_layout(const evlb_params* p) {
   for (int s = 0; s < p->n_sys; ++s) L.ntot += p->nx[s];
   L.ntiles_wide = count_tiles(p, WIDE);
   L.ntiles_narrow = count_tiles(p, NARROW);
+  L.ntiles_col = count_tiles(p, WC);
   L.ms = (int)llround(p->sigma / p->dx);
   L.mf = p->force_model == EVLB_FORCE_EV1 ? (int)llround(p->r_cut / p->dx) : 0;
   const int q = p->q;
@@ -644,6 +911,8 @@ Layout make_layout(const evlb_params* p) {
   off += align256(sizeof(int4) * (size_t)L.ntiles_wide);
   L.tiles_narrow = off;
   off += align256(sizeof(int4) * (size_t)L.ntiles_narrow);
+  L.tiles_col = off;
+  off += align256(sizeof(int4) * (size_t)L.ntiles_col);
   const size_t fbytes = align256(sizeof(double) * 2 * (size_t)q * (size_t)L.ntot);
   L.f1 = off; off += fbytes;
   L.f2 = off; off += fbytes;
@@ -682,12 +951,14 @@ template <> struct WideNG<8> { static constexpr int v = 4; };
 template <> struct WideNG<16> { static constexpr int v = 8; };
 template <> struct WideNG<24> { static constexpr int v = 8; };
 
-template <int W>
-DevParams params_for(const evlb_ctx* c) {
+DevParams params_for(const evlb_ctx* c, int w) {
   DevParams P = c->dp;
-  if (W == NARROW) {
+  if (w == NARROW) {
     P.tiles = (const int4*)(c->ws + c->L.tiles_narrow);
     P.ntiles = c->L.ntiles_narrow;
+  } else if (w == WC) {
+    P.tiles = (const int4*)(c->ws + c->L.tiles_col);
+    P.ntiles = c->L.ntiles_col;
   } else {
     P.tiles = (const int4*)(c->ws + c->L.tiles_wide);
     P.ntiles = c->L.ntiles_wide;
@@ -697,17 +968,24 @@ DevParams params_for(const evlb_ctx* c) {
 
 template <int Q, int W, int NG>
 int launch_stage(evlb_ctx* c, const StageArgs& A, hipStream_t st) {
-  const DevParams P = params_for<W>(c);
+  const DevParams P = params_for(c, W);
   hipLaunchKernelGGL((stage_kernel<Q, W, NG>), dim3(P.ntiles), dim3(W * NG), 0, st, P, A);
   return hipGetLastError() == hipSuccess ? EVLB_OK : EVLB_EHIP;
 }
 
-template <int Q, int W, int NG>
-int launch_persistent(evlb_ctx* c, double* f, int nsteps, hipStream_t st) {
+template <int Q>
+int launch_stage_col(evlb_ctx* c, const StageArgs& A, hipStream_t st) {
+  const DevParams P = params_for(c, WC);
+  hipLaunchKernelGGL((stage_kernel_col<Q>), dim3(P.ntiles), dim3(64), 0, st, P, A, P.vel, P.meq, P.dpm);
+  return hipGetLastError() == hipSuccess ? EVLB_OK : EVLB_EHIP;
+}
+
+template <class SHAPE>
+int launch_persistent(evlb_ctx* c, int width, double* f, int nsteps, hipStream_t st) {
   int per_cu = 0;
-  EVLB_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, persistent_kernel<Q, W, NG>, W * NG, 0));
+  EVLB_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, persistent_kernel<SHAPE>, SHAPE::NT, 0));
   if (per_cu < 1) return EVLB_EHIP;
-  DevParams P = params_for<W>(c);
+  DevParams P = params_for(c, width);
   int grid = per_cu * c->cus;
   if (grid > P.ntiles) grid = P.ntiles;
   PersistArgs R;
@@ -719,9 +997,11 @@ int launch_persistent(evlb_ctx* c, double* f, int nsteps, hipStream_t st) {
   R.nsteps = nsteps;
   hipLaunchKernelGGL(clear_barrier_kernel, dim3(1), dim3(64), 0, st, P);
   EVLB_HIP(hipGetLastError());
-  void* args[] = {&P, &R};
-  EVLB_HIP(hipLaunchCooperativeKernel((const void*)persistent_kernel<Q, W, NG>, dim3(grid), dim3(W * NG), args, 0,
-                                      st));
+  const double* vel = P.vel;
+  const double* meq = P.meq;
+  const double* dpm = P.dpm;
+  void* args[] = {&P, &R, &vel, &meq, &dpm};
+  EVLB_HIP(hipLaunchCooperativeKernel((const void*)persistent_kernel<SHAPE>, dim3(grid), dim3(SHAPE::NT), args, 0, st));
   return EVLB_OK;
 }
 
@@ -733,40 +1013,57 @@ int run_moments(evlb_ctx* c, const double* f, double* n, double* u, double* T, d
   return hipGetLastError() == hipSuccess ? EVLB_OK : EVLB_EHIP;
 }
 
-// tile width: explicit, or narrow when wide tiles cannot occupy every CU twice
+// tile shape: explicit, or the column shape when it yields at least four
+// wavefronts per CU, else the narrow shape (small grids, latency bound)
 int pick_width(const evlb_ctx* c) {
   if (c->p.tile_nodes) return c->p.tile_nodes;
-  return c->L.ntiles_wide >= 4 * c->cus ? WIDE : NARROW;
+  return c->L.ntiles_col >= 4 * c->cus ? WC : NARROW;
 }
 
-template <int Q, int W, int NG>
-int run_step_shape(evlb_ctx* c, double* f, int nsteps, hipStream_t st) {
+StageArgs stage_args(double* f, double* f1, double* f2, double* momA, double* momB, int step, int s) {
+  const double a_s[3] = {0.0, 0.75, 1.0 / 3.0};
+  const double b_s[3] = {1.0, 0.25, 2.0 / 3.0};
+  StageArgs A;
+  A.f_prev = s == 0 ? f : (s == 1 ? f1 : f2);
+  A.f_n = f;
+  A.f_out = s == 0 ? f1 : (s == 1 ? f2 : f);
+  const int parity = (step * 3 + s) & 1;
+  A.mom_in = parity ? momB : momA;
+  A.mom_out = parity ? momA : momB;
+  A.alpha = a_s[s];
+  A.beta = b_s[s];
+  A.first = s == 0;
+  A.rhs_mode = 0;
+  return A;
+}
+
+template <int Q>
+int launch_stage_w(evlb_ctx* c, int w, const StageArgs& A, hipStream_t st) {
+  if (w == NARROW) return launch_stage<Q, NARROW, Q>(c, A, st);
+  if (w == WC) return launch_stage_col<Q>(c, A, st);
+  return launch_stage<Q, WIDE, WideNG<Q>::v>(c, A, st);
+}
+
+template <int Q>
+int run_step(evlb_ctx* c, double* f, int nsteps, hipStream_t st) {
   const long long nt = c->L.ntot;
   double* momA = (double*)(c->ws + c->L.momA);
   double* momB = (double*)(c->ws + c->L.momB);
   int rc = run_moments<Q>(c, f, momA, momA + nt, momA + 2 * nt, momA + 3 * nt, st);
   if (rc) return rc;
+  const int w = pick_width(c);
   int mode = c->p.exec_mode;
   if (mode == EVLB_EXEC_AUTO) mode = EVLB_EXEC_PER_STAGE;
-  if (mode == EVLB_EXEC_PERSISTENT) return launch_persistent<Q, W, NG>(c, f, nsteps, st);
+  if (mode == EVLB_EXEC_PERSISTENT) {
+    if (w == NARROW) return launch_persistent<GroupShape<Q, NARROW, Q>>(c, w, f, nsteps, st);
+    if (w == WC) return launch_persistent<ColumnShape<Q>>(c, w, f, nsteps, st);
+    return launch_persistent<GroupShape<Q, WIDE, WideNG<Q>::v>>(c, w, f, nsteps, st);
+  }
   double* f1 = (double*)(c->ws + c->L.f1);
   double* f2 = (double*)(c->ws + c->L.f2);
-  const double a_s[3] = {0.0, 0.75, 1.0 / 3.0};
-  const double b_s[3] = {1.0, 0.25, 2.0 / 3.0};
   for (int step = 0; step < nsteps; ++step) {
     for (int s = 0; s < 3; ++s) {
-      StageArgs A;
-      A.f_prev = s == 0 ? f : (s == 1 ? f1 : f2);
-      A.f_n = f;
-      A.f_out = s == 0 ? f1 : (s == 1 ? f2 : f);
-      const int parity = (step * 3 + s) & 1;
-      A.mom_in = parity ? momB : momA;
-      A.mom_out = parity ? momA : momB;
-      A.alpha = a_s[s];
-      A.beta = b_s[s];
-      A.first = s == 0;
-      A.rhs_mode = 0;
-      rc = launch_stage<Q, W, NG>(c, A, st);
+      rc = launch_stage_w<Q>(c, w, stage_args(f, f1, f2, momA, momB, step, s), st);
       if (rc) return rc;
     }
   }
@@ -774,13 +1071,7 @@ int run_step_shape(evlb_ctx* c, double* f, int nsteps, hipStream_t st) {
 }
 
 template <int Q>
-int run_step(evlb_ctx* c, double* f, int nsteps, hipStream_t st) {
-  if (pick_width(c) == NARROW) return run_step_shape<Q, NARROW, Q>(c, f, nsteps, st);
-  return run_step_shape<Q, WIDE, WideNG<Q>::v>(c, f, nsteps, st);
-}
-
-template <int Q, int W, int NG>
-int run_rhs_shape(evlb_ctx* c, const double* f, double* L, hipStream_t st) {
+int run_rhs(evlb_ctx* c, const double* f, double* L, hipStream_t st) {
   const long long nt = c->L.ntot;
   double* momA = (double*)(c->ws + c->L.momA);
   double* momB = (double*)(c->ws + c->L.momB);
@@ -796,13 +1087,7 @@ int run_rhs_shape(evlb_ctx* c, const double* f, double* L, hipStream_t st) {
   A.beta = 1.0;
   A.first = 1;
   A.rhs_mode = 1;
-  return launch_stage<Q, W, NG>(c, A, st);
-}
-
-template <int Q>
-int run_rhs(evlb_ctx* c, const double* f, double* L, hipStream_t st) {
-  if (pick_width(c) == NARROW) return run_rhs_shape<Q, NARROW, Q>(c, f, L, st);
-  return run_rhs_shape<Q, WIDE, WideNG<Q>::v>(c, f, L, st);
+  return launch_stage_w<Q>(c, pick_width(c), A, st);
 }
 
 template <int Q>
@@ -867,11 +1152,12 @@ int evlb_init(const evlb_params* params, void* d_workspace, size_t ws_bytes, voi
   host.insert(host.end(), t.dpm.begin(), t.dpm.end());
   host.insert(host.end(), t.savg.begin(), t.savg.end());
   host.insert(host.end(), t.cfor.begin(), t.cfor.end());
-  std::vector<int4> tw, tn;
+  std::vector<int4> tw, tn, tc;
   int off = 0;
   for (int s = 0; s < params->n_sys; ++s) {
     for (int i0 = 0; i0 < params->nx[s]; i0 += WIDE) tw.push_back(make_int4(off, params->nx[s], i0, 0));
     for (int i0 = 0; i0 < params->nx[s]; i0 += NARROW) tn.push_back(make_int4(off, params->nx[s], i0, 0));
+    for (int i0 = 0; i0 < params->nx[s]; i0 += WC) tc.push_back(make_int4(off, params->nx[s], i0, 0));
     off += params->nx[s];
   }
   hipStream_t st = (hipStream_t)hip_stream;
@@ -880,6 +1166,7 @@ int evlb_init(const evlb_params* params, void* d_workspace, size_t ws_bytes, voi
   if (hipMemcpy(tab, host.data(), host.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(c->ws + L.tiles_wide, tw.data(), tw.size() * sizeof(int4), hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(c->ws + L.tiles_narrow, tn.data(), tn.size() * sizeof(int4), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(c->ws + L.tiles_col, tc.data(), tc.size() * sizeof(int4), hipMemcpyHostToDevice) != hipSuccess ||
       hipMemset(c->ws + L.status, 0, 256) != hipSuccess) {
     delete c;
     return EVLB_EHIP;

@@ -78,7 +78,7 @@ def test_equilibrium_and_moments_match_oracle():
             assert np.max(np.abs(mom[i] - ref[i])) <= 1e-13 * np.max(np.abs(ref[i])) + 1e-16, i
 
 
-@pytest.mark.parametrize("tile", [16, 64])
+@pytest.mark.parametrize("tile", [16, 63, 64])
 @pytest.mark.parametrize("mask", [1, 2, 4, 8, 15])
 @pytest.mark.parametrize("which", ["phase", "slab"])
 def test_rhs_matches_oracle_per_term(mask, which, tile):
@@ -92,7 +92,7 @@ def test_rhs_matches_oracle_per_term(mask, which, tile):
     assert rel(L, [LF, LG]) < 1e-11
 
 
-@pytest.mark.parametrize("tile", [16, 64])
+@pytest.mark.parametrize("tile", [16, 63, 64])
 @pytest.mark.parametrize("mode", [1, 2])
 def test_one_and_ten_steps_match_oracle(mode, tile):
     for c, n, u, T in (case_phase(), case_slab()):
@@ -128,7 +128,7 @@ def test_phase_separation_1000_steps_match_oracle():
 def test_exec_modes_agree_and_repeat_bitwise():
     c, n, u, T = case_slab(2048)
     out = []
-    for mode, tile in ((1, 64), (2, 64), (1, 64), (1, 16), (2, 16)):
+    for mode, tile in ((1, 64), (2, 64), (1, 64), (1, 16), (2, 16), (1, 63), (2, 63)):
         s = solver(c, exec_mode=mode, tile_nodes=tile)
         f = s.equilibrium(td(n), td(u), td(T))
         s.step(f, 20)
@@ -146,7 +146,7 @@ def test_ragged_batch_matches_independent_oracle_runs():
     n = np.concatenate([s[0] for s in systems])
     u = np.concatenate([s[1] for s in systems])
     T = np.concatenate([s[2] for s in systems])
-    for mode, tile in ((1, 64), (2, 64), (1, 16), (2, 16)):
+    for mode, tile in ((1, 64), (2, 64), (1, 16), (2, 16), (1, 63), (2, 63)):
         s = solver(c, nx=nxs, exec_mode=mode, tile_nodes=tile)
         f = s.equilibrium(td(n), td(u), td(T))
         s.step(f, 5)
