@@ -6,10 +6,15 @@ velocities, dx = sigma/8, liquid slab 64 sigma wide (eq:tan) at the
 coexistence densities of T/T_c = 0.8.  The metric counts site-velocity
 updates per second: nodes x velocities x 3 stages x steps / GPU time.
 
-Prints one JSON line (see the fields below).  The state is resident in HBM
-before the timed region; timing uses HIP events on the stream the kernels run
-on.  The CPU baseline is the oracle timed on a bounded number of steps of
-the same workload on one host core.
+A secondary entry reports the batched sweep (512 independent periodic systems
+of log-uniform length in [256, 8192], Q = 16, about 1.1M nodes), the
+HBM-sized case, with its own roofline.
+
+Prints one JSON line.  The state is resident in HBM before the timed region;
+timing uses HIP events on the stream the kernels run on.  The launch shape of
+each workload is chosen by the autotuner before timing.  The CPU baseline is
+the oracle timed on a bounded number of steps of the headline workload on one
+host core.
 """
 import argparse
 import json
@@ -23,10 +28,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-BYTES_PER_UPDATE_STEP = 128.0   # per site-velocity per RK3 step (F and G)
+BYTES_PER_UPDATE_STEP = 128.0   # per site-velocity per RK3 step (F and G): see the design doc
+KERNEL_NAMES = {16: "stage_kernel<{q},16,{q}>", 63: "stage_kernel_col<{q}>", 64: "stage_kernel<{q},64,8>"}
 
 
-def cpu_baseline(c, n, u, T, target_s=12.0):
+def cpu_baseline(c, n, u, T, target_s=15.0):
     """Oracle (numpy FP64, one thread) on a bounded sample of steps."""
     try:
         from threadpoolctl import threadpool_limits
@@ -34,24 +40,79 @@ def cpu_baseline(c, n, u, T, target_s=12.0):
         threadpool_limits = None
     from oracle import step1d
     from oracle.model import Params
-    ctxm = threadpool_limits(1) if threadpool_limits else None
+    lim = threadpool_limits(1) if threadpool_limits else None
     try:
         tb = step1d.Tables(Params(Q=c["Q"], dx=c["dx"], dt=c["dt"]))
         F, G = step1d.initial_state(n, u, T, tb)
+        F, G = step1d.rk3_step(F, G, tb)           # warm caches
         t0 = time.perf_counter()
-        F, G = step1d.rk3_step(F, G, tb)
-        t1 = time.perf_counter() - t0
-        steps = max(1, int(target_s / max(t1, 1e-6)))
+        for _ in range(3):
+            F, G = step1d.rk3_step(F, G, tb)
+        per = (time.perf_counter() - t0) / 3
+        steps = max(3, int(target_s / per))
         t0 = time.perf_counter()
         for _ in range(steps):
             F, G = step1d.rk3_step(F, G, tb)
         el = time.perf_counter() - t0
     finally:
-        if ctxm is not None:
-            ctxm.__exit__(None, None, None)
+        if lim is not None:
+            lim.__exit__(None, None, None)
     rate = c["nx"] * c["Q"] * 3 * steps / el
     return {"value": rate, "unit": "updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"{steps} RK3 steps of the {c['nx']}x{c['Q']} slab workload ({el:.1f} s, numpy FP64, 1 thread)"}
+            "sample": f"{steps} RK3 steps of the {c['nx']}-node Q={c['Q']} slab workload "
+                      f"({el:.1f} s, numpy FP64, 1 thread)"}
+
+
+def default_tile(nx, cus=256):
+    """The library's automatic tile choice: column tiles when they give at
+    least four wavefronts per CU, else narrow 16-node tiles."""
+    nxs = [nx] if isinstance(nx, int) else list(nx)
+    return 63 if sum((v + 62) // 63 for v in nxs) >= 4 * cus else 16
+
+
+def measure(E, torch, dev, q, dx, dt, nx, n, u, T, steps, warmup, mode=None, tile=None):
+    from paper_2503_15187_amd import autotune
+    td = lambda a: torch.tensor(a, dtype=torch.float64, device=dev)
+    n_tot = int(np.sum(nx))
+    if mode is None or tile is None:
+        probe = E.Solver(q, dx, dt, nx, device=dev)
+        f0 = probe.equilibrium(td(n), td(u), td(T))
+        mode, tile, _ = autotune.tune(q, dx, dt, nx, f0, steps=max(5, min(50, steps // 20)), use_cache=False)
+        del probe
+    s = E.Solver(q, dx, dt, nx, device=dev, exec_mode=mode, tile_nodes=tile)
+    f = s.equilibrium(td(n), td(u), td(T))
+    stream = torch.cuda.current_stream()
+    if warmup:
+        s.step(f, warmup)
+    torch.cuda.synchronize()
+    if s.status() != 0:
+        raise RuntimeError("non-finite state during warm-up")
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    s.step(f, steps)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_s = ev0.elapsed_time(ev1) / 1e3
+    if s.status() != 0:
+        raise RuntimeError("device status not ok after the timed run")
+    updates = n_tot * q * 3 * steps
+    persistent = mode == E.EVLB_EXEC_PERSISTENT
+    launches = 1 if persistent else 3 * steps
+    kname = KERNEL_NAMES[tile].format(q=q)
+    if persistent:
+        kname = f"persistent_kernel<{kname}>"
+    alg_bytes = BYTES_PER_UPDATE_STEP * n_tot * q * steps / launches
+    achieved = alg_bytes / (gpu_s / launches) / 1e9
+    return {
+        "value": updates / gpu_s, "gpu_s": gpu_s, "wall_s": wall, "ms_per_step": gpu_s * 1e3 / steps,
+        "exec": "persistent" if persistent else "per_stage", "tile_nodes": tile,
+        "roofline": {"bound": "hbm", "kernel": kname, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "bytes_per_launch": alg_bytes, "avg_launch_us": gpu_s / launches * 1e6},
+    }
 
 
 def main():
@@ -59,8 +120,15 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None, help="timed RK3 steps (default: the workload's 20000)")
     ap.add_argument("--warmup", type=int, default=200)
-    ap.add_argument("--exec-mode", type=int, default=0, help="0 auto, 1 per stage, 2 persistent")
+    ap.add_argument("--exec-mode", type=int, default=None, help="1 per stage, 2 persistent (default: autotune)")
+    ap.add_argument("--tile", type=int, default=None, help="16, 63 or 64 (default: autotune)")
+    ap.add_argument("--batch-steps", type=int, default=100)
+    ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="use the library's default launch shape (one kernel per stage) instead of timing candidates")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="after timing, run one 256 MiB device-to-device copy (a reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only; the multi-GPU (domain-decomposed) path is "
@@ -75,63 +143,50 @@ def main():
     torch.cuda.set_device(dev)
     c, n, u, T = workloads.slab_1d()
     steps = args.steps if args.steps is not None else c["steps"]
-    s = E.Solver(c["Q"], c["dx"], c["dt"], c["nx"], device=dev, exec_mode=args.exec_mode)
-    td = lambda a: torch.tensor(a, dtype=torch.float64, device=dev)
-    f = s.equilibrium(td(n), td(u), td(T))
-    stream = torch.cuda.current_stream()
-    if args.warmup:
-        s.step(f, args.warmup)
-    torch.cuda.synchronize()
-    if s.status() != 0:
-        raise RuntimeError("non-finite state during warm-up")
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ev0.record(stream)
-    s.step(f, steps)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    gpu_s = ev0.elapsed_time(ev1) / 1e3
-    status = s.status()
-    if status != 0:
-        raise RuntimeError(f"device status {status} after the timed run")
-
-    updates = c["nx"] * c["Q"] * 3 * steps
-    value = updates / gpu_s
-    # dominant kernel: the whole step loop runs in one persistent launch (auto
-    # mode for this size), so one launch moves 128 B per site-velocity per step
-    persistent = args.exec_mode == 2 or (args.exec_mode == 0 and (c["nx"] + 63) // 64 <= 2 * 256)
-    if persistent:
-        launches = 1
-        kernel = "persistent_kernel<24,8>"
-    else:
-        launches = 3 * steps
-        kernel = "stage_kernel<24,8>"
-    alg_bytes = BYTES_PER_UPDATE_STEP * c["nx"] * c["Q"] * steps / launches
-    dur = gpu_s / launches
-    achieved = alg_bytes / dur / 1e9
+    mode, tile = args.exec_mode, args.tile
+    if args.no_autotune:
+        mode, tile = E.EVLB_EXEC_PER_STAGE, default_tile(c["nx"])
+    m = measure(E, torch, dev, c["Q"], c["dx"], c["dt"], c["nx"], n, u, T, steps, args.warmup, mode, tile)
     out = {
         "metric": "site-velocity updates/s per RK stage (FP64)",
-        "value": value,
+        "value": m["value"],
         "unit": "updates/s",
         "n_gpus": 1,
         "steps": steps,
         "warmup": args.warmup,
-        "ms_per_step": gpu_s * 1e3 / steps,
+        "ms_per_step": m["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": "slab_evaporation_1d", "nx": c["nx"], "q": c["Q"], "dx": c["dx"],
-                   "dt": c["dt"], "T": c["T"], "exec": "persistent" if persistent else "per_stage"},
-        "roofline": {"bound": "hbm", "kernel": kernel, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None},
-        "hbm_peak_frac": achieved / HBM_PEAK_GBS,
-        "wall_s": wall,
+                   "dt": c["dt"], "T": c["T"], "exec": m["exec"], "tile_nodes": m["tile_nodes"]},
+        "roofline": m["roofline"],
+        "hbm_peak_frac": m["roofline"]["frac"],
+        "wall_s": m["wall_s"],
     }
+    if not args.no_batch:
+        cb, systems = workloads.batched_sweep_1d()
+        nb = np.concatenate([x[0] for x in systems])
+        ub = np.concatenate([x[1] for x in systems])
+        Tb = np.concatenate([x[2] for x in systems])
+        bmode = btile = None
+        if args.no_autotune:
+            bmode, btile = E.EVLB_EXEC_PER_STAGE, default_tile(cb["nx_list"])
+        mb = measure(E, torch, dev, cb["Q"], cb["dx"], cb["dt"], cb["nx_list"], nb, ub, Tb,
+                     args.batch_steps, 5, bmode, btile)
+        out["secondary"] = [{
+            "config": {"workload": "batched_sweep_1d", "n_sys": cb["n_sys"], "n_tot": int(len(nb)), "q": cb["Q"],
+                       "dx": cb["dx"], "exec": mb["exec"], "tile_nodes": mb["tile_nodes"]},
+            "steps": args.batch_steps, "value": mb["value"], "unit": "updates/s", "ms_per_step": mb["ms_per_step"],
+            "roofline": mb["roofline"]}]
+    if args.calibrate_copy:
+        x = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device=dev)
+        y = torch.empty_like(x)
+        y.copy_(x)
+        torch.cuda.synchronize()
+        del x, y
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(c, n, u, T)
     print(json.dumps(out), flush=True)
