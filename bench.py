@@ -63,6 +63,23 @@ def cpu_baseline(c, n, u, T, target_s=15.0):
                       f"({el:.1f} s, numpy FP64, 1 thread)"}
 
 
+def measured_traffic(workload, kernel):
+    """HBM bytes per launch from the committed counter runs (profiles/
+    hbm_traffic.txt), or None when the kernel source changed since."""
+    import hashlib
+    try:
+        with open(os.path.join(ROOT, "profiles", "hbm_traffic.txt")) as fh:
+            rec = json.load(fh)
+        with open(os.path.join(ROOT, rec["source"]), "rb") as fh:
+            sha = hashlib.sha256(fh.read()).hexdigest()
+    except (OSError, ValueError, KeyError):
+        return None
+    if sha != rec.get("source_sha256"):
+        return None
+    e = rec["entries"].get(f"{workload}/{kernel}")
+    return None if e is None else e["bytes_per_launch"]
+
+
 def default_tile(nx, cus=256):
     """The library's automatic tile choice: column tiles when they give at
     least four wavefronts per CU, else narrow 16-node tiles."""
@@ -162,7 +179,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": "slab_evaporation_1d", "nx": c["nx"], "q": c["Q"], "dx": c["dx"],
                    "dt": c["dt"], "T": c["T"], "exec": m["exec"], "tile_nodes": m["tile_nodes"]},
-        "roofline": m["roofline"],
+        "roofline": dict(m["roofline"], traffic=measured_traffic("slab_evaporation_1d", m["roofline"]["kernel"])),
         "hbm_peak_frac": m["roofline"]["frac"],
         "wall_s": m["wall_s"],
     }
@@ -180,7 +197,7 @@ def main():
             "config": {"workload": "batched_sweep_1d", "n_sys": cb["n_sys"], "n_tot": int(len(nb)), "q": cb["Q"],
                        "dx": cb["dx"], "exec": mb["exec"], "tile_nodes": mb["tile_nodes"]},
             "steps": args.batch_steps, "value": mb["value"], "unit": "updates/s", "ms_per_step": mb["ms_per_step"],
-            "roofline": mb["roofline"]}]
+            "roofline": dict(mb["roofline"], traffic=measured_traffic("batched_sweep_1d", mb["roofline"]["kernel"]))}]
     if args.calibrate_copy:
         x = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device=dev)
         y = torch.empty_like(x)
