@@ -94,7 +94,8 @@ typedef struct {
   double weno_eps;       /* WENO-5 epsilon, 1e-6                             */
   double g_ext;          /* uniform external acceleration (tests), usually 0 */
   int32_t exec_mode;     /* EVLB_EXEC_*                                      */
-  int32_t tile_nodes;    /* nodes per workgroup tile: 0 = auto, 16 or 64     */
+  int32_t tile_nodes;    /* nodes per workgroup tile: 0 = auto, 16, 63 or 64 */
+  int32_t adjoint;       /* 1: size the workspace for evlb_adjoint_step      */
 } evlb_params;
 
 typedef struct evlb_ctx evlb_ctx; /* opaque, host memory */
@@ -140,6 +141,28 @@ int evlb_rhs(evlb_ctx* ctx, const double* d_f, double* d_L, void* hip_stream);
  * Outputs device [n_tot]; d_q may be NULL. */
 int evlb_moments(evlb_ctx* ctx, const double* d_f, double* d_n, double* d_u,
                  double* d_T, double* d_q, void* hip_stream);
+
+/* Discrete adjoint of one evlb_step step (rows of the method as above, the
+ * TVD-RK3 scheme transposed stage by stage).  Given d_lam_np1 = dL/df^{n+1}
+ * for the state after the step and d_f_n = the state before it, writes
+ * d_lam_n = dL/df^n through the step, and ADDS to d_dparams[0..1] the
+ * explicit derivatives dL/dphi_sigma and dL/dsigma of this step (the node
+ * window of the averaged density stays fixed; the kernel switches branch at
+ * |x' - x| >= sigma, so the sigma derivative is the one-sided derivative from
+ * below where a node sits on sigma).  All pointers are device: d_f_n,
+ * d_lam_np1, d_lam_n [2][q][n_tot], d_dparams [2].  d_lam_n must not alias
+ * d_lam_np1 or d_f_n.  Requires params.adjoint = 1 and force model EV1 or
+ * none (EVLB_EINVAL otherwise).  The stage buffers of the workspace are
+ * overwritten. */
+int evlb_adjoint_step(evlb_ctx* ctx, const double* d_f_n, const double* d_lam_np1,
+                      double* d_lam_n, double* d_dparams, void* hip_stream);
+
+/* Adjoint of evlb_set_equilibrium: for lam = dL/df (device [2][q][n_tot])
+ * writes dL/dn, dL/du, dL/dT (device [n_tot] each) of the state
+ * F = E(n, u, T), G = T E. */
+int evlb_equilibrium_adjoint(evlb_ctx* ctx, const double* d_n, const double* d_u,
+                             const double* d_T, const double* d_lam, double* d_nbar,
+                             double* d_ubar, double* d_Tbar, void* hip_stream);
 
 /* Synchronises hip_stream and reports the latched device status:
  * EVLB_OK or EVLB_ENONFINITE.  Clears the latch when clear != 0. */

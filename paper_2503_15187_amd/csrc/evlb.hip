@@ -46,6 +46,9 @@ struct DevParams {
   const double* dpm;   // [q][q]
   const double* savg;  // [2 ms + 1]
   const double* cfor;  // [mf]
+  const double* cphi;  // [mf] d cfor / d phi_sigma
+  const double* csig;  // [mf] d cfor / d sigma
+  const double* ssig;  // [2 ms + 1] d savg / d sigma
   const int4* tiles;   // {system offset, system nodes, tile start, 0}
   int ntiles;
   int ms, mf, hn;
@@ -54,6 +57,7 @@ struct DevParams {
   double b;        // 2 pi sigma^3 / 3
   double eta_c;    // pi sigma^3 / 6
   double mu0c;     // 5 / (16 sigma^2 sqrt(pi)):  mu0 = mu0c sqrt(T)
+  double sigma;
   double weno_eps, g_ext, two_a, kappa;
   int force_model, term_mask;
   int* status;     // [0] non-finite latch, [1] barrier abort latch
@@ -835,15 +839,19 @@ __global__ __launch_bounds__(256) void equilibrium_kernel(DevParams P, const dou
 // host side
 // ---------------------------------------------------------------------------
 
+#include "adjoint.inc"
+
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 constexpr int WIDE = 64;    // tile width for large grids
 constexpr int NARROW = 16;  // tile width for grids too small to fill the chip
 
 struct Layout {
-  size_t tables, tiles_wide, tiles_narrow, tiles_col, f1, f2, momA, momB, status, total;
+  size_t tables, tiles_wide, tiles_narrow, tiles_col, tiles_adj, f1, f2, momA, momB, status;
+  size_t adj_g, adj_mu2, adj_mu1, adj_fa, adj_fb, adj_mom, adj_part, total;
   long long ntot;
-  int ntiles_wide, ntiles_narrow, ntiles_col, ms, mf;
+  int ntiles_wide, ntiles_narrow, ntiles_col, ntiles_adj, ms, mf;
+  size_t ntables;
 };
 
 int count_tiles(const evlb_params* p, int w) {
@@ -880,6 +888,8 @@ int validate(const evlb_params* p) {
   if (p->term_mask & ~EVLB_TERM_ALL) return EVLB_EINVAL;
   if (!(p->weno_eps > 0) || !std::isfinite(p->g_ext)) return EVLB_EINVAL;
   if (p->exec_mode < 0 || p->exec_mode > 2) return EVLB_EINVAL;
+  if (p->adjoint != 0 && p->adjoint != 1) return EVLB_EINVAL;
+  if (p->adjoint && p->force_model == EVLB_FORCE_EV2) return EVLB_EUNSUPPORTED;
   if (p->tile_nodes != 0 && p->tile_nodes != WIDE && p->tile_nodes != NARROW && p->tile_nodes != WC)
     return EVLB_EINVAL;
   int ms, mf = 0;
@@ -901,18 +911,23 @@ Layout make_layout(const evlb_params* p) {
   L.ntiles_wide = count_tiles(p, WIDE);
   L.ntiles_narrow = count_tiles(p, NARROW);
   L.ntiles_col = count_tiles(p, WC);
+  L.ntiles_adj = count_tiles(p, WA);
   L.ms = (int)llround(p->sigma / p->dx);
   L.mf = p->force_model == EVLB_FORCE_EV1 ? (int)llround(p->r_cut / p->dx) : 0;
   const int q = p->q;
   size_t off = 0;
   L.tables = off;
-  off += align256(sizeof(double) * (size_t)(q + 2 * q * q + 2 * L.ms + 1 + (L.mf > 0 ? L.mf : 1)));
+  const int mfa = L.mf > 0 ? L.mf : 1;
+  L.ntables = (size_t)(q + 2 * q * q + 2 * (2 * L.ms + 1) + 3 * mfa);
+  off += align256(sizeof(double) * L.ntables);
   L.tiles_wide = off;
   off += align256(sizeof(int4) * (size_t)L.ntiles_wide);
   L.tiles_narrow = off;
   off += align256(sizeof(int4) * (size_t)L.ntiles_narrow);
   L.tiles_col = off;
   off += align256(sizeof(int4) * (size_t)L.ntiles_col);
+  L.tiles_adj = off;
+  off += align256(sizeof(int4) * (size_t)L.ntiles_adj);
   const size_t fbytes = align256(sizeof(double) * 2 * (size_t)q * (size_t)L.ntot);
   L.f1 = off; off += fbytes;
   L.f2 = off; off += fbytes;
@@ -920,6 +935,15 @@ Layout make_layout(const evlb_params* p) {
   L.momA = off; off += mbytes;
   L.momB = off; off += mbytes;
   L.status = off; off += 256;
+  if (p->adjoint) {
+    L.adj_g = off; off += fbytes;
+    L.adj_mu2 = off; off += fbytes;
+    L.adj_mu1 = off; off += fbytes;
+    L.adj_fa = off; off += align256(sizeof(double) * NFA * (size_t)L.ntot);
+    L.adj_fb = off; off += align256(sizeof(double) * NFB * (size_t)L.ntot);
+    L.adj_mom = off; off += mbytes;
+    L.adj_part = off; off += align256(sizeof(double) * 2 * 6 * (size_t)L.ntiles_adj);
+  }
   L.total = off;
   return L;
 }
@@ -1097,6 +1121,95 @@ int run_equilibrium(evlb_ctx* c, const double* n, const double* u, const double*
   return hipGetLastError() == hipSuccess ? EVLB_OK : EVLB_EHIP;
 }
 
+
+// ---- adjoint step -----------------------------------------------------------
+
+DevParams params_adj(const evlb_ctx* c) {
+  DevParams P = c->dp;
+  P.tiles = (const int4*)(c->ws + c->L.tiles_adj);
+  P.ntiles = c->L.ntiles_adj;
+  return P;
+}
+
+// g = (dL/df)^T v at state f (moments mom), written as
+// out = cc (v + dt g) + a1 X1 + a2 X2; parameter partials weighted by pw into
+// slots [2 * vjp_index, 2 * vjp_index + 1] of the partial buffer.
+template <int Q>
+int launch_vjp(evlb_ctx* c, const double* f, const double* mom, const double* v, double* out, const double* X1,
+               const double* X2, double cc, double a1, double a2, double pw, int vjp_index, hipStream_t st) {
+  const DevParams P = params_adj(c);
+  AdjArgs A;
+  A.f = f;
+  A.mom = mom;
+  A.v = v;
+  A.gdir = (double*)(c->ws + c->L.adj_g);
+  A.fa = (double*)(c->ws + c->L.adj_fa);
+  A.fb = (double*)(c->ws + c->L.adj_fb);
+  A.out = out;
+  A.X1 = X1;
+  A.X2 = X2;
+  A.c = cc;
+  A.a1 = a1;
+  A.a2 = a2;
+  A.pw = pw;
+  double* part = (double*)(c->ws + c->L.adj_part);
+  const int nta = P.ntiles;
+  A.part = part + (size_t)(2 * vjp_index) * 2 * nta;
+  hipLaunchKernelGGL((adj_fields_kernel<Q>), dim3(nta), dim3(64), 0, st, P, A, P.vel, P.meq, P.dpm);
+  EVLB_HIP(hipGetLastError());
+  A.part = part + (size_t)(2 * vjp_index + 1) * 2 * nta;
+  hipLaunchKernelGGL((adj_gather_kernel<Q>), dim3(nta), dim3(64), 0, st, P, A);
+  EVLB_HIP(hipGetLastError());
+  hipLaunchKernelGGL((adj_column_kernel<Q>), dim3(nta), dim3(64), 0, st, P, A, P.vel);
+  EVLB_HIP(hipGetLastError());
+  return EVLB_OK;
+}
+
+template <int Q>
+int run_adjoint(evlb_ctx* c, const double* fn, const double* lam3, double* lam0, double* dparams, hipStream_t st) {
+  const long long nt = c->L.ntot;
+  double* momA = (double*)(c->ws + c->L.momA);
+  double* momB = (double*)(c->ws + c->L.momB);
+  double* f1 = (double*)(c->ws + c->L.f1);
+  double* f2 = (double*)(c->ws + c->L.f2);
+  double* mu2 = (double*)(c->ws + c->L.adj_mu2);
+  double* mu1 = (double*)(c->ws + c->L.adj_mu1);
+  double* amom = (double*)(c->ws + c->L.adj_mom);
+  const double dt = c->p.dt;
+  // recompute the two inner stages: f1 (moments in momB), f2 (moments in momA)
+  int rc = run_moments<Q>(c, fn, momA, momA + nt, momA + 2 * nt, momA + 3 * nt, st);
+  if (rc) return rc;
+  const int w = pick_width(c);
+  for (int s = 0; s < 2; ++s) {
+    rc = launch_stage_w<Q>(c, w, stage_args(const_cast<double*>(fn), f1, f2, momA, momB, 0, s), st);
+    if (rc) return rc;
+  }
+  rc = run_moments<Q>(c, fn, amom, amom + nt, amom + 2 * nt, amom + 3 * nt, st);
+  if (rc) return rc;
+  // f^{n+1} = 1/3 f^n + 2/3 (f2 + dt L(f2)):   mu2 = 2/3 (lam3 + dt J(f2)^T lam3)
+  rc = launch_vjp<Q>(c, f2, momA, lam3, mu2, nullptr, nullptr, 2.0 / 3.0, 0.0, 0.0, dt * 2.0 / 3.0, 0, st);
+  if (rc) return rc;
+  // f2 = 3/4 f^n + 1/4 (f1 + dt L(f1)):          mu1 = 1/4 (mu2 + dt J(f1)^T mu2)
+  rc = launch_vjp<Q>(c, f1, momB, mu2, mu1, nullptr, nullptr, 0.25, 0.0, 0.0, dt * 0.25, 1, st);
+  if (rc) return rc;
+  // f1 = f^n + dt L(f^n):  lam^n = mu1 + dt J(f^n)^T mu1 + 1/3 lam3 + 3/4 mu2
+  rc = launch_vjp<Q>(c, fn, amom, mu1, lam0, lam3, mu2, 1.0, 1.0 / 3.0, 0.75, dt, 2, st);
+  if (rc) return rc;
+  hipLaunchKernelGGL(adj_reduce_kernel, dim3(1), dim3(64), 0, st, (const double*)(c->ws + c->L.adj_part),
+                     6 * c->L.ntiles_adj, dparams);
+  EVLB_HIP(hipGetLastError());
+  return EVLB_OK;
+}
+
+template <int Q>
+int run_equilibrium_adjoint(evlb_ctx* c, const double* n, const double* u, const double* T, const double* lam,
+                            double* nb, double* ub, double* Tb, hipStream_t st) {
+  const int blocks = (int)((c->L.ntot + 255) / 256);
+  hipLaunchKernelGGL((equilibrium_adjoint_kernel<Q>), dim3(blocks), dim3(256), 0, st, c->dp, n, u, T, lam, nb, ub,
+                     Tb);
+  return hipGetLastError() == hipSuccess ? EVLB_OK : EVLB_EHIP;
+}
+
 #define EVLB_DISPATCH_Q(q, fn, ...)              \
   switch (q) {                                   \
     case 8: return fn<8>(__VA_ARGS__);           \
@@ -1143,7 +1256,11 @@ int evlb_init(const evlb_params* params, void* d_workspace, size_t ws_bytes, voi
   evlb::TableParams tp{params->q, params->dx, params->sigma, params->phi_sigma, params->gamma, params->r_cut};
   evlb::HostTables t;
   evlb::build_tables(tp, t);
-  if (params->force_model != EVLB_FORCE_EV1) t.cfor.assign(1, 0.0);
+  if (params->force_model != EVLB_FORCE_EV1) {
+    t.cfor.assign(1, 0.0);
+    t.cphi.assign(1, 0.0);
+    t.csig.assign(1, 0.0);
+  }
   c->vel = t.vel;
   const int q = params->q;
   std::vector<double> host;
@@ -1152,12 +1269,16 @@ int evlb_init(const evlb_params* params, void* d_workspace, size_t ws_bytes, voi
   host.insert(host.end(), t.dpm.begin(), t.dpm.end());
   host.insert(host.end(), t.savg.begin(), t.savg.end());
   host.insert(host.end(), t.cfor.begin(), t.cfor.end());
-  std::vector<int4> tw, tn, tc;
+  host.insert(host.end(), t.cphi.begin(), t.cphi.end());
+  host.insert(host.end(), t.csig.begin(), t.csig.end());
+  host.insert(host.end(), t.ssig.begin(), t.ssig.end());
+  std::vector<int4> tw, tn, tc, ta;
   int off = 0;
   for (int s = 0; s < params->n_sys; ++s) {
     for (int i0 = 0; i0 < params->nx[s]; i0 += WIDE) tw.push_back(make_int4(off, params->nx[s], i0, 0));
     for (int i0 = 0; i0 < params->nx[s]; i0 += NARROW) tn.push_back(make_int4(off, params->nx[s], i0, 0));
     for (int i0 = 0; i0 < params->nx[s]; i0 += WC) tc.push_back(make_int4(off, params->nx[s], i0, 0));
+    for (int i0 = 0; i0 < params->nx[s]; i0 += WA) ta.push_back(make_int4(off, params->nx[s], i0, 0));
     off += params->nx[s];
   }
   hipStream_t st = (hipStream_t)hip_stream;
@@ -1167,6 +1288,7 @@ int evlb_init(const evlb_params* params, void* d_workspace, size_t ws_bytes, voi
       hipMemcpy(c->ws + L.tiles_wide, tw.data(), tw.size() * sizeof(int4), hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(c->ws + L.tiles_narrow, tn.data(), tn.size() * sizeof(int4), hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(c->ws + L.tiles_col, tc.data(), tc.size() * sizeof(int4), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(c->ws + L.tiles_adj, ta.data(), ta.size() * sizeof(int4), hipMemcpyHostToDevice) != hipSuccess ||
       hipMemset(c->ws + L.status, 0, 256) != hipSuccess) {
     delete c;
     return EVLB_EHIP;
@@ -1177,7 +1299,11 @@ int evlb_init(const evlb_params* params, void* d_workspace, size_t ws_bytes, voi
   d.meq = tab + q;
   d.dpm = tab + q + q * q;
   d.savg = tab + q + 2 * q * q;
+  const int nc = (int)t.cfor.size();
   d.cfor = tab + q + 2 * q * q + 2 * L.ms + 1;
+  d.cphi = d.cfor + nc;
+  d.csig = d.cphi + nc;
+  d.ssig = d.csig + nc;
   d.tiles = (const int4*)(c->ws + L.tiles_wide);
   d.ntiles = L.ntiles_wide;
   d.ms = L.ms;
@@ -1191,6 +1317,7 @@ int evlb_init(const evlb_params* params, void* d_workspace, size_t ws_bytes, voi
   d.b = 2.0 * M_PI * sg * sg * sg / 3.0;
   d.eta_c = M_PI * sg * sg * sg / 6.0;
   d.mu0c = 5.0 / (16.0 * sg * sg * std::sqrt(M_PI));
+  d.sigma = sg;
   d.weno_eps = params->weno_eps;
   d.g_ext = params->g_ext;
   const double g = params->gamma;
@@ -1229,6 +1356,23 @@ int evlb_moments(evlb_ctx* ctx, const double* d_f, double* d_n, double* d_u, dou
   if (!ctx || !d_f || !d_n || !d_u || !d_T) return EVLB_EINVAL;
   if (!device_matches(ctx)) return EVLB_EINVAL;
   EVLB_DISPATCH_Q(ctx->p.q, run_moments, ctx, d_f, d_n, d_u, d_T, d_q, (hipStream_t)hip_stream);
+}
+
+int evlb_adjoint_step(evlb_ctx* ctx, const double* d_f_n, const double* d_lam_np1, double* d_lam_n,
+                      double* d_dparams, void* hip_stream) {
+  if (!ctx || !d_f_n || !d_lam_np1 || !d_lam_n || !d_dparams) return EVLB_EINVAL;
+  if (!ctx->p.adjoint) return EVLB_EINVAL;
+  if (d_lam_n == d_lam_np1 || (const double*)d_lam_n == d_f_n) return EVLB_EINVAL;
+  if (!device_matches(ctx)) return EVLB_EINVAL;
+  EVLB_DISPATCH_Q(ctx->p.q, run_adjoint, ctx, d_f_n, d_lam_np1, d_lam_n, d_dparams, (hipStream_t)hip_stream);
+}
+
+int evlb_equilibrium_adjoint(evlb_ctx* ctx, const double* d_n, const double* d_u, const double* d_T,
+                             const double* d_lam, double* d_nbar, double* d_ubar, double* d_Tbar, void* hip_stream) {
+  if (!ctx || !d_n || !d_u || !d_T || !d_lam || !d_nbar || !d_ubar || !d_Tbar) return EVLB_EINVAL;
+  if (!device_matches(ctx)) return EVLB_EINVAL;
+  EVLB_DISPATCH_Q(ctx->p.q, run_equilibrium_adjoint, ctx, d_n, d_u, d_T, d_lam, d_nbar, d_ubar, d_Tbar,
+                  (hipStream_t)hip_stream);
 }
 
 int evlb_status(evlb_ctx* ctx, void* hip_stream, int32_t clear) {

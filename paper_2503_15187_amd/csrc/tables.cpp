@@ -121,11 +121,15 @@ void build_tables(const TableParams& tp, HostTables& t) {
   const int ms = (int)std::lround(tp.sigma / tp.dx);
   t.ms = ms;
   t.savg.assign(2 * ms + 1, 0.0);
+  t.ssig.assign(2 * ms + 1, 0.0);
   for (int j = -ms; j <= ms; ++j) {
     ld s = (ld)j * tp.dx;
     ld sg = tp.sigma;
     t.savg[j + ms] = (double)(3.0L / (4.0L * sg * sg * sg) * (sg * sg - s * s) * (ld)tp.dx *
                               (ld)simpson(j + ms, 2 * ms));
+    // the node window stays fixed when sigma varies; the weights follow it
+    t.ssig[j + ms] = (double)((3.0L / (2.0L * sg * sg) - 9.0L * (sg * sg - s * s) / (4.0L * sg * sg * sg * sg)) *
+                              (ld)tp.dx * (ld)simpson(j + ms, 2 * ms));
   }
 
   // EV1 force, eq:F1 by composite Simpson on |s| <= r_cut:
@@ -134,12 +138,18 @@ void build_tables(const TableParams& tp, HostTables& t) {
   const int mf = (int)std::lround(tp.r_cut / tp.dx);
   t.mf = mf;
   t.cfor.assign(mf, 0.0);
+  t.cphi.assign(mf, 0.0);
+  t.csig.assign(mf, 0.0);
   const ld pi = 3.141592653589793238462643383279502884L;
   for (int j = 1; j <= mf; ++j) {
     ld s = (ld)j * tp.dx;
-    ld ratio = (s < (ld)tp.sigma) ? 1.0L : std::pow((ld)tp.sigma / s, (ld)tp.gamma);
-    t.cfor[j - 1] = (double)(2.0L * pi * (ld)tp.phi * s * ratio * (ld)tp.dx *
-                             (ld)simpson(j + mf, 2 * mf));
+    const bool outer = !(s < (ld)tp.sigma);
+    ld ratio = outer ? std::pow((ld)tp.sigma / s, (ld)tp.gamma) : 1.0L;
+    const ld unit = 2.0L * pi * s * ratio * (ld)tp.dx * (ld)simpson(j + mf, 2 * mf);
+    t.cfor[j - 1] = (double)((ld)tp.phi * unit);
+    t.cphi[j - 1] = (double)unit;
+    // outer branch: K ~ sigma^gamma; inner branch independent of sigma
+    t.csig[j - 1] = outer ? (double)((ld)tp.phi * unit * (ld)tp.gamma / (ld)tp.sigma) : 0.0;
   }
 }
 

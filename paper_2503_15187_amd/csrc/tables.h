@@ -15,6 +15,9 @@ struct HostTables {
   std::vector<double> meq, dpm;   // [q*q], row k = velocity
   std::vector<double> savg;       // [2*ms+1]
   std::vector<double> cfor;       // [mf], j = 1..mf
+  std::vector<double> cphi;       // [mf] d cfor_j / d phi
+  std::vector<double> csig;       // [mf] d cfor_j / d sigma
+  std::vector<double> ssig;       // [2*ms+1] d savg_j / d sigma
   int ms = 0, mf = 0;
 };
 

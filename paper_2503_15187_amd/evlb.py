@@ -40,6 +40,7 @@ class evlb_params(ctypes.Structure):
         ("g_ext", ctypes.c_double),
         ("exec_mode", ctypes.c_int32),
         ("tile_nodes", ctypes.c_int32),
+        ("adjoint", ctypes.c_int32),
     ]
 
 
@@ -60,6 +61,8 @@ _SIGS = {
     "evlb_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
     "evlb_rhs": (ctypes.c_int, [ctypes.c_void_p] * 4),
     "evlb_moments": (ctypes.c_int, [ctypes.c_void_p] * 7),
+    "evlb_adjoint_step": (ctypes.c_int, [ctypes.c_void_p] * 6),
+    "evlb_equilibrium_adjoint": (ctypes.c_int, [ctypes.c_void_p] * 9),
     "evlb_status": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32]),
     "evlb_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64), ctypes.c_void_p]),
     "evlb_destroy": (None, [ctypes.c_void_p]),
@@ -94,14 +97,14 @@ def _check(code, what):
 
 def make_params(q, dx, dt, nx, sigma=1.0, phi_sigma=1.0, gamma=6.0, r_cut=5.0,
                 force_model=EVLB_FORCE_EV1, term_mask=EVLB_TERM_ALL, weno_eps=1e-6,
-                g_ext=0.0, exec_mode=EVLB_EXEC_AUTO, tile_nodes=0):
+                g_ext=0.0, exec_mode=EVLB_EXEC_AUTO, tile_nodes=0, adjoint=0):
     """evlb_params for one or several periodic 1D systems (nx: int or list).
     The returned structure keeps its nx array alive."""
     nxs = [int(nx)] if isinstance(nx, (int,)) else [int(v) for v in nx]
     arr = (ctypes.c_int32 * len(nxs))(*nxs)
     p = evlb_params(EVLB_ABI_VERSION, 1, len(nxs), arr, int(q), float(dx), float(dt), float(sigma),
                     float(phi_sigma), float(gamma), float(r_cut), int(force_model), int(term_mask),
-                    float(weno_eps), float(g_ext), int(exec_mode), int(tile_nodes))
+                    float(weno_eps), float(g_ext), int(exec_mode), int(tile_nodes), int(adjoint))
     p._nx_keepalive = arr
     return p
 
@@ -156,6 +159,17 @@ def evlb_rhs(ctx, f, L, stream=None):
 def evlb_moments(ctx, f, n, u, T, q=None, stream=None):
     _check(lib().evlb_moments(ctx, _dptr(f, "f"), _dptr(n, "n"), _dptr(u, "u"), _dptr(T, "T"),
                               _dptr(q, "q"), _stream(stream)), "evlb_moments")
+
+
+def evlb_adjoint_step(ctx, f_n, lam_np1, lam_n, dparams, stream=None):
+    _check(lib().evlb_adjoint_step(ctx, _dptr(f_n, "f_n"), _dptr(lam_np1, "lam_np1"), _dptr(lam_n, "lam_n"),
+                                   _dptr(dparams, "dparams"), _stream(stream)), "evlb_adjoint_step")
+
+
+def evlb_equilibrium_adjoint(ctx, n, u, T, lam, nbar, ubar, Tbar, stream=None):
+    _check(lib().evlb_equilibrium_adjoint(ctx, _dptr(n, "n"), _dptr(u, "u"), _dptr(T, "T"), _dptr(lam, "lam"),
+                                          _dptr(nbar, "nbar"), _dptr(ubar, "ubar"), _dptr(Tbar, "Tbar"),
+                                          _stream(stream)), "evlb_equilibrium_adjoint")
 
 
 def evlb_status(ctx, stream=None, clear=True):
@@ -221,3 +235,15 @@ class Solver:
 
     def status(self, stream=None):
         return evlb_status(self.ctx, stream)
+
+    def adjoint_step(self, f_n, lam_np1, dparams, stream=None):
+        """lam_n = dL/df^n through one step; dparams (device [2]) += explicit
+        dL/dphi_sigma, dL/dsigma of the step."""
+        lam_n = torch.empty_like(lam_np1)
+        evlb_adjoint_step(self.ctx, f_n, lam_np1, lam_n, dparams, stream)
+        return lam_n
+
+    def equilibrium_adjoint(self, n, u, T, lam, stream=None):
+        out = torch.empty((3, self.n_tot), dtype=torch.float64, device=self.device)
+        evlb_equilibrium_adjoint(self.ctx, n, u, T, lam, out[0], out[1], out[2], stream)
+        return out
