@@ -132,6 +132,48 @@ def measure(E, torch, dev, q, dx, dt, nx, n, u, T, steps, warmup, mode=None, til
     }
 
 
+def adjoint_ratio(E, torch, dev, nsteps):
+    """Adjoint workload: 2048 nodes, dx = sigma/4, Q = 16, slab at T = 0.85
+    T_c; loss = time-integrated flux through x = 128 sigma + final misfit.
+    Times the forward rollout (per-step flux recorded, sqrt(N) checkpoints)
+    and the backward pass (segment recompute + discrete adjoint steps)."""
+    import workloads
+    from paper_2503_15187_amd import adjoint as AD
+    c, n0, u0, T0 = workloads.slab_1d(name="adjoint_slab_1d")
+    target = workloads.adjoint_target(c, n0)
+    i_f = c["nx"] // 2 + int(round(c["x_flux"] / c["dx"]))
+    s = E.Solver(c["Q"], c["dx"], c["dt"], c["nx"], device=dev, adjoint=1)
+    td = lambda a: torch.tensor(a, dtype=torch.float64, device=dev)
+    n0t = td(n0).requires_grad_(True)
+    phi = torch.tensor(1.0, dtype=torch.float64, device=dev, requires_grad=True)
+    sig = torch.tensor(1.0, dtype=torch.float64, device=dev, requires_grad=True)
+    # warm-up
+    L = AD.slab_loss(n0t, phi, sig, s, 20, i_f, c["dt"], c["dx"], td(target), td(T0))
+    torch.autograd.grad(L, [n0t, phi, sig])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    L = AD.slab_loss(n0t, phi, sig, s, nsteps, i_f, c["dt"], c["dx"], td(target), td(T0))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    g = torch.autograd.grad(L, [n0t, phi, sig])
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    f = s.equilibrium(td(n0), td(u0), td(T0))
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    s.step(f, nsteps)
+    torch.cuda.synchronize()
+    t4 = time.perf_counter()
+    if s.status() != 0:
+        raise RuntimeError("device status not ok in the adjoint workload")
+    return {"config": {"workload": "adjoint_slab_1d", "nx": c["nx"], "q": c["Q"], "dx": c["dx"], "steps": nsteps,
+                       "checkpoint_every": int(np.ceil(np.sqrt(nsteps)))},
+            "metric": "adjoint/forward time", "value": (t2 - t1) / (t1 - t0), "unit": "ratio",
+            "forward_s": t1 - t0, "backward_s": t2 - t1, "plain_forward_s": t4 - t3,
+            "ratio_vs_plain_forward": (t2 - t1) / (t4 - t3),
+            "grad": {"dL_dphi": g[1].item(), "dL_dsigma": g[2].item(), "dL_dn0_norm": g[0].norm().item()}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -142,6 +184,8 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=100)
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--adjoint-steps", type=int, default=2000)
     ap.add_argument("--no-autotune", action="store_true",
                     help="use the library's default launch shape (one kernel per stage) instead of timing candidates")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -198,6 +242,8 @@ def main():
                        "dx": cb["dx"], "exec": mb["exec"], "tile_nodes": mb["tile_nodes"]},
             "steps": args.batch_steps, "value": mb["value"], "unit": "updates/s", "ms_per_step": mb["ms_per_step"],
             "roofline": dict(mb["roofline"], traffic=measured_traffic("batched_sweep_1d", mb["roofline"]["kernel"]))}]
+    if not args.no_adjoint:
+        out["secondary"] = out.get("secondary", []) + [adjoint_ratio(E, torch, dev, args.adjoint_steps)]
     if args.calibrate_copy:
         x = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device=dev)
         y = torch.empty_like(x)

@@ -83,7 +83,8 @@ typedef struct {
   int32_t n_sys;         /* >= 1 independent periodic systems                */
   const int32_t* nx;     /* host [n_sys]: nodes per system, each >= 8        */
   int32_t q;             /* Gauss-Hermite order: 8, 16 or 24                 */
-  double dx;             /* grid spacing; sigma/dx and r_cut/dx even ints    */
+  double dx;             /* grid spacing; r_cut/dx an even integer, sigma/dx  
+                            within 1e-3 of one (the averaging window)        */
   double dt;             /* time step                                        */
   double sigma;          /* hard-sphere diameter (eq:sutherland)             */
   double phi_sigma;      /* well depth of the attractive tail                */

@@ -860,10 +860,10 @@ int count_tiles(const evlb_params* p, int w) {
   return t;
 }
 
-bool is_even_multiple(double a, double dx, int* m) {
+bool is_even_multiple(double a, double dx, int* m, double tol = 1e-9) {
   const double r = a / dx;
   const long long k = llround(r);
-  if (k <= 0 || std::fabs(r - (double)k) > 1e-9 * r || (k & 1)) return false;
+  if (k <= 0 || std::fabs(r - (double)k) > tol * r || (k & 1)) return false;
   *m = (int)k;
   return true;
 }
@@ -893,7 +893,9 @@ int validate(const evlb_params* p) {
   if (p->tile_nodes != 0 && p->tile_nodes != WIDE && p->tile_nodes != NARROW && p->tile_nodes != WC)
     return EVLB_EINVAL;
   int ms, mf = 0;
-  if (!is_even_multiple(p->sigma, p->dx, &ms) || ms > MS_MAX) return EVLB_EINVAL;
+  // the averaging window is the nearest even number of cells; sigma may sit
+  // slightly off it (derivatives with respect to sigma at a fixed window)
+  if (!is_even_multiple(p->sigma, p->dx, &ms, 1e-3) || ms > MS_MAX) return EVLB_EINVAL;
   if (p->force_model == EVLB_FORCE_EV1) {
     if (!is_even_multiple(p->r_cut, p->dx, &mf) || mf > MF_MAX) return EVLB_EINVAL;
   }

@@ -176,3 +176,41 @@ def test_slab_loss_gradients_match_complex_step():
     assert abs(gsig.item() - ref_sig) <= 1e-9 * abs(ref_sig)
     gdir = float(np.sum(gn.cpu().numpy() * dirv))
     assert abs(gdir - ref_n) <= 1e-9 * np.sum(np.abs(gn.cpu().numpy() * dirv))
+
+
+def test_full_size_adjoint_gradients_match_finite_differences():
+    """Adjoint workload at full size (2048 nodes, dx = sigma/4, Q = 16, slab
+    at 0.85 T_c, flux node x = 128 sigma) over 400 steps: adjoint gradients
+    against finite differences of the GPU loss (central in phi_sigma and in a
+    direction of the initial density; second-order backward in sigma, whose
+    kernel has a node on the branch point |x' - x| = sigma, third order))."""
+    c, n0, u0, T0 = workloads.slab_1d(name="adjoint_slab_1d")
+    target = workloads.adjoint_target(c, n0)
+    i_f = c["nx"] // 2 + int(round(c["x_flux"] / c["dx"]))
+    nsteps = 400
+
+    def loss(phi=1.0, sigma=1.0, dn=None, grad=False):
+        s = E.Solver(c["Q"], c["dx"], c["dt"], c["nx"], phi_sigma=phi, sigma=sigma, adjoint=1)
+        n = td(n0 if dn is None else n0 + dn)
+        if grad:
+            n.requires_grad_(True)
+        ph = torch.tensor(phi, dtype=torch.float64, device="cuda", requires_grad=grad)
+        sg = torch.tensor(sigma, dtype=torch.float64, device="cuda", requires_grad=grad)
+        L = AD.slab_loss(n, ph, sg, s, nsteps, i_f, c["dt"], c["dx"], td(target), td(T0))
+        if grad:
+            return L.item(), torch.autograd.grad(L, [n, ph, sg])
+        return L.item()
+
+    L0, (gn, gphi, gsig) = loss(grad=True)
+    h = 1e-5
+    fd_phi = (loss(phi=1 + h) - loss(phi=1 - h)) / (2 * h)
+    # third-order backward difference (the sigma derivative is one-sided)
+    fd_sig = (11 * L0 - 18 * loss(sigma=1 - h) + 9 * loss(sigma=1 - 2 * h) - 2 * loss(sigma=1 - 3 * h)) / (6 * h)
+    dirv = np.random.default_rng(11).standard_normal(len(n0)) * 1e-3
+    fd_n = (loss(dn=h * dirv) - loss(dn=-h * dirv)) / (2 * h)
+    gd = float(np.sum(gn.cpu().numpy() * dirv))
+    print(f"phi {gphi.item():.10e} fd {fd_phi:.10e}; sigma {gsig.item():.10e} fd {fd_sig:.10e}; "
+          f"n0 {gd:.10e} fd {fd_n:.10e}", flush=True)
+    assert abs(gphi.item() - fd_phi) <= 1e-6 * abs(fd_phi)
+    assert abs(gsig.item() - fd_sig) <= 1e-6 * abs(fd_sig)
+    assert abs(gd - fd_n) <= 1e-6 * abs(fd_n)
