@@ -158,6 +158,29 @@ int evlb_moments(evlb_ctx* ctx, const double* d_f, double* d_n, double* d_u,
 int evlb_adjoint_step(evlb_ctx* ctx, const double* d_f_n, const double* d_lam_np1,
                       double* d_lam_n, double* d_dparams, void* hip_stream);
 
+/* Number of doubles of one step record of evlb_step_record: the state, the
+ * two inner Runge-Kutta stage states and the moments of the three,
+ * 3 * 2 * q * n_tot + 12 * n_tot. */
+int64_t evlb_record_doubles(const evlb_ctx* ctx);
+
+/* Advances d_f0 (device [2][q][n_tot], read only) by nsteps steps, keeping
+ * every step: d_rec (device, (nsteps + 1) * evlb_record_doubles) receives
+ * record j = {f^j, f1^j, f2^j, moments of the three} for j < nsteps, and
+ * record nsteps starts with f^nsteps (its stages are left unwritten). */
+int evlb_step_record(evlb_ctx* ctx, const double* d_f0, int32_t nsteps, double* d_rec,
+                     void* hip_stream);
+
+/* Runs evlb_adjoint_step backwards over a record of nsteps steps without
+ * recomputing stages.  d_lam (device [2][q][n_tot]) holds dL/df^nsteps on
+ * entry and dL/df^0 on return.  Optional per-step linear observable: with
+ * d_obs (device [2][q][n_tot]) and d_w (device [nsteps]), the loss is taken
+ * to contain sum_j w[j] <d_obs, f^{j+1}>, i.e. dL/df^{j+1} += w[j] d_obs
+ * before step j is transposed (both NULL: none).  d_dparams as for
+ * evlb_adjoint_step. */
+int evlb_adjoint_record(evlb_ctx* ctx, const double* d_rec, int32_t nsteps, double* d_lam,
+                        const double* d_obs, const double* d_w, double* d_dparams,
+                        void* hip_stream);
+
 /* Adjoint of evlb_set_equilibrium: for lam = dL/df (device [2][q][n_tot])
  * writes dL/dn, dL/du, dL/dT (device [n_tot] each) of the state
  * F = E(n, u, T), G = T E. */

@@ -2,11 +2,12 @@
 
 Rollout (a torch.autograd.Function) advances a state nsteps TVD-RK3 steps
 and returns the final state together with the history of the mass flux
-sum_k p_k F_k through one node after every step.  Its backward pass walks the
-steps in reverse with evlb_adjoint_step, recomputing the forward states of
-each segment from checkpoints stored every ceil(sqrt(nsteps)) steps, and
-returns the gradients with respect to the initial state and to the
-parameters phi_sigma and sigma (the latter two enter as 0-d tensors whose
+sum_k p_k F_k through one node after every step.  The forward pass keeps a
+checkpoint every ceil(sqrt(nsteps)) steps.  The backward pass re-runs each
+segment from its checkpoint with evlb_step_record (states and stage states
+kept) and transposes it with evlb_adjoint_record, walking the segments in
+reverse; it returns the gradients with respect to the initial state and to
+the parameters phi_sigma and sigma (the latter two enter as 0-d tensors whose
 values must equal the context's; they only carry the gradient).
 
 Equilibrium maps (n, u, T) fields to the initial reduced Maxwellian with
@@ -36,15 +37,23 @@ class Rollout(torch.autograd.Function):
     def forward(ctx, f0, phi, sigma, solver, nsteps, flux_node, every=None):
         nsteps = int(nsteps)
         every = int(every) if every else max(1, int(math.ceil(math.sqrt(nsteps))))
-        vel = torch.tensor(solver.velocities, dtype=torch.float64, device=f0.device)
-        f = f0.detach().clone().contiguous()
-        ckpt = {0: f.clone()}
-        flux = torch.empty(nsteps, dtype=torch.float64, device=f0.device)
-        for s in range(1, nsteps + 1):
-            solver.step(f, 1)
-            flux[s - 1] = (vel * f[0, :, flux_node]).sum()
-            if s % every == 0 and s < nsteps:
-                ckpt[s] = f.clone()
+        dev = f0.device
+        vel = torch.tensor(solver.velocities, dtype=torch.float64, device=dev)
+        rec = solver.record_buffer(every)
+        R = rec.numel() // (every + 1)
+        N = solver.n_tot
+        # offsets of F_k(flux_node) inside a record, k = 0..q-1
+        kofs = torch.arange(solver.q, device=dev) * N + flux_node
+        f = f0.detach().contiguous()
+        ckpt = {}
+        flux = torch.empty(nsteps, dtype=torch.float64, device=dev)
+        for start in range(0, nsteps, every):
+            seg = min(every, nsteps - start)
+            ckpt[start] = f.clone()
+            solver.step_record(f, seg, rec)
+            idx = (torch.arange(1, seg + 1, device=dev) * R)[:, None] + kofs[None, :]
+            flux[start:start + seg] = rec[idx] @ vel
+            f = solver.record_state(rec, seg).clone()
         ctx.solver, ctx.nsteps, ctx.every, ctx.flux_node = solver, nsteps, every, flux_node
         ctx.ckpt, ctx.vel = ckpt, vel
         return f, flux
@@ -53,19 +62,17 @@ class Rollout(torch.autograd.Function):
     def backward(ctx, g_f, g_flux):
         solver, nsteps, every, node = ctx.solver, ctx.nsteps, ctx.every, ctx.flux_node
         lam = torch.zeros_like(ctx.ckpt[0]) if g_f is None else g_f.detach().clone().contiguous()
-        gfl = None if g_flux is None else g_flux.detach()
+        obs = w = None
+        if g_flux is not None:
+            obs = torch.zeros_like(lam)
+            obs[0, :, node] = ctx.vel
+            w = g_flux.detach().contiguous()
         dparams = torch.zeros(2, dtype=torch.float64, device=lam.device)
+        rec = solver.record_buffer(every)
         for start in sorted(ctx.ckpt, reverse=True):
-            end = min(start + every, nsteps)
-            states = [ctx.ckpt[start]]
-            f = ctx.ckpt[start].clone()
-            for _ in range(start, end - 1):
-                solver.step(f, 1)
-                states.append(f.clone())
-            for n in range(end - 1, start - 1, -1):
-                if gfl is not None:
-                    lam[0, :, node] += gfl[n] * ctx.vel
-                lam = solver.adjoint_step(states[n - start], lam, dparams)
+            seg = min(every, nsteps - start)
+            solver.step_record(ctx.ckpt[start], seg, rec)
+            solver.adjoint_record(rec, seg, lam, dparams, obs, None if w is None else w[start:start + seg])
         return lam, dparams[0], dparams[1], None, None, None, None
 
 

@@ -848,7 +848,7 @@ constexpr int NARROW = 16;  // tile width for grids too small to fill the chip
 
 struct Layout {
   size_t tables, tiles_wide, tiles_narrow, tiles_col, tiles_adj, f1, f2, momA, momB, status;
-  size_t adj_g, adj_mu2, adj_mu1, adj_fa, adj_fb, adj_mom, adj_part, total;
+  size_t adj_g, adj_mu2, adj_mu1, adj_fa, adj_fb, adj_mom, adj_part, adj_lam, total;
   long long ntot;
   int ntiles_wide, ntiles_narrow, ntiles_col, ntiles_adj, ms, mf;
   size_t ntables;
@@ -945,6 +945,7 @@ Layout make_layout(const evlb_params* p) {
     L.adj_fb = off; off += align256(sizeof(double) * NFB * (size_t)L.ntot);
     L.adj_mom = off; off += mbytes;
     L.adj_part = off; off += align256(sizeof(double) * 2 * 6 * (size_t)L.ntiles_adj);
+    L.adj_lam = off; off += fbytes;
   }
   L.total = off;
   return L;
@@ -1138,7 +1139,9 @@ DevParams params_adj(const evlb_ctx* c) {
 // slots [2 * vjp_index, 2 * vjp_index + 1] of the partial buffer.
 template <int Q>
 int launch_vjp(evlb_ctx* c, const double* f, const double* mom, const double* v, double* out, const double* X1,
-               const double* X2, double cc, double a1, double a2, double pw, int vjp_index, hipStream_t st) {
+               const double* X2, double cc, double a1, double a2, double pw, int vjp_index, hipStream_t st,
+               double* vinj = nullptr, const double* obs = nullptr, const double* wts = nullptr, int j = 0,
+               bool final_reduce = false, double* dparams = nullptr) {
   const DevParams P = params_adj(c);
   AdjArgs A;
   A.f = f;
@@ -1154,17 +1157,45 @@ int launch_vjp(evlb_ctx* c, const double* f, const double* mom, const double* v,
   A.a1 = a1;
   A.a2 = a2;
   A.pw = pw;
+  A.vinj = vinj;
+  A.obs = obs;
+  A.w = wts;
+  A.j = j;
   double* part = (double*)(c->ws + c->L.adj_part);
   const int nta = P.ntiles;
   A.part = part + (size_t)(2 * vjp_index) * 2 * nta;
-  hipLaunchKernelGGL((adj_fields_kernel<Q>), dim3(nta), dim3(64), 0, st, P, A, P.vel, P.meq, P.dpm);
+  hipLaunchKernelGGL((adj_fields_kernel<Q>), dim3(nta), dim3(64 * NWA), 0, st, P, A, P.vel, P.meq, P.dpm);
   EVLB_HIP(hipGetLastError());
   A.part = part + (size_t)(2 * vjp_index + 1) * 2 * nta;
-  hipLaunchKernelGGL((adj_gather_kernel<Q>), dim3(nta), dim3(64), 0, st, P, A);
+  hipLaunchKernelGGL((adj_node_kernel<Q>), dim3(nta), dim3(64 * NWT), 0, st, P, A, P.vel, final_reduce ? 1 : 0,
+                     (const double*)part, 6 * nta, dparams);
   EVLB_HIP(hipGetLastError());
-  hipLaunchKernelGGL((adj_column_kernel<Q>), dim3(nta), dim3(64), 0, st, P, A, P.vel);
+  hipLaunchKernelGGL((adj_column_kernel<Q>), dim3(nta * (2 * Q / ADJ_ROWS)), dim3(64), 0, st, P, A, P.vel);
   EVLB_HIP(hipGetLastError());
   return EVLB_OK;
+}
+
+// One adjoint step given the step's states f^n, f1, f2 and their moments.
+template <int Q>
+int adjoint_core(evlb_ctx* c, const double* fn, const double* mn, const double* f1, const double* m1,
+                 const double* f2, const double* m2, const double* lam3, double* lam0, double* dparams,
+                 hipStream_t st, double* lam3_inject = nullptr, const double* obs = nullptr,
+                 const double* wts = nullptr, int j = 0) {
+  double* mu2 = (double*)(c->ws + c->L.adj_mu2);
+  double* mu1 = (double*)(c->ws + c->L.adj_mu1);
+  const double dt = c->p.dt;
+  // f^{n+1} = 1/3 f^n + 2/3 (f2 + dt L(f2)):   mu2 = 2/3 (lam3 + dt J(f2)^T lam3)
+  // (with an observable: lam3 += w[j] obs first, stored back into lam3)
+  int rc = launch_vjp<Q>(c, f2, m2, lam3, mu2, nullptr, nullptr, 2.0 / 3.0, 0.0, 0.0, dt * 2.0 / 3.0, 0, st,
+                         lam3_inject, obs, wts, j);
+  if (rc) return rc;
+  // f2 = 3/4 f^n + 1/4 (f1 + dt L(f1)):          mu1 = 1/4 (mu2 + dt J(f1)^T mu2)
+  rc = launch_vjp<Q>(c, f1, m1, mu2, mu1, nullptr, nullptr, 0.25, 0.0, 0.0, dt * 0.25, 1, st);
+  if (rc) return rc;
+  // f1 = f^n + dt L(f^n):  lam^n = mu1 + dt J(f^n)^T mu1 + 1/3 lam3 + 3/4 mu2
+  // (its final kernel adds the step's parameter derivatives to dparams)
+  return launch_vjp<Q>(c, fn, mn, mu1, lam0, lam3, mu2, 1.0, 1.0 / 3.0, 0.75, dt, 2, st, nullptr, nullptr, nullptr, 0,
+                       true, dparams);
 }
 
 template <int Q>
@@ -1174,32 +1205,80 @@ int run_adjoint(evlb_ctx* c, const double* fn, const double* lam3, double* lam0,
   double* momB = (double*)(c->ws + c->L.momB);
   double* f1 = (double*)(c->ws + c->L.f1);
   double* f2 = (double*)(c->ws + c->L.f2);
-  double* mu2 = (double*)(c->ws + c->L.adj_mu2);
-  double* mu1 = (double*)(c->ws + c->L.adj_mu1);
   double* amom = (double*)(c->ws + c->L.adj_mom);
-  const double dt = c->p.dt;
   // recompute the two inner stages: f1 (moments in momB), f2 (moments in momA)
-  int rc = run_moments<Q>(c, fn, momA, momA + nt, momA + 2 * nt, momA + 3 * nt, st);
+  int rc = run_moments<Q>(c, fn, amom, amom + nt, amom + 2 * nt, amom + 3 * nt, st);
   if (rc) return rc;
   const int w = pick_width(c);
-  for (int s = 0; s < 2; ++s) {
-    rc = launch_stage_w<Q>(c, w, stage_args(const_cast<double*>(fn), f1, f2, momA, momB, 0, s), st);
-    if (rc) return rc;
+  StageArgs A0 = stage_args(const_cast<double*>(fn), f1, f2, momA, momB, 0, 0);
+  A0.mom_in = amom;
+  rc = launch_stage_w<Q>(c, w, A0, st);
+  if (rc) return rc;
+  rc = launch_stage_w<Q>(c, w, stage_args(const_cast<double*>(fn), f1, f2, momA, momB, 0, 1), st);
+  if (rc) return rc;
+  return adjoint_core<Q>(c, fn, amom, f1, momB, f2, momA, lam3, lam0, dparams, st);
+}
+
+// Record layout of one step j: f^j, f1^j, f2^j ([2][q][n] each), then the
+// moments of the three ([4][n] each).
+size_t record_doubles(const evlb_ctx* c) {
+  const size_t fs = 2 * (size_t)c->p.q * (size_t)c->L.ntot;
+  return 3 * fs + 3 * 4 * (size_t)c->L.ntot;
+}
+
+template <int Q>
+int run_step_record(evlb_ctx* c, const double* f0, int nsteps, double* rec, hipStream_t st) {
+  const size_t fs = 2 * (size_t)Q * (size_t)c->L.ntot;
+  const size_t R = record_doubles(c);
+  const long long nt = c->L.ntot;
+  EVLB_HIP(hipMemcpyAsync(rec, f0, fs * sizeof(double), hipMemcpyDeviceToDevice, st));
+  double* m0 = rec + 3 * fs;
+  int rc = run_moments<Q>(c, rec, m0, m0 + nt, m0 + 2 * nt, m0 + 3 * nt, st);
+  if (rc) return rc;
+  const int w = pick_width(c);
+  const double a_s[3] = {0.0, 0.75, 1.0 / 3.0};
+  const double b_s[3] = {1.0, 0.25, 2.0 / 3.0};
+  for (int j = 0; j < nsteps; ++j) {
+    double* r = rec + (size_t)j * R;
+    double* rn = rec + (size_t)(j + 1) * R;
+    double* fj[3] = {r, r + fs, r + 2 * fs};
+    double* mj[3] = {r + 3 * fs, r + 3 * fs + 4 * nt, r + 3 * fs + 8 * nt};
+    for (int s = 0; s < 3; ++s) {
+      StageArgs A;
+      A.f_prev = fj[s];
+      A.f_n = fj[0];
+      A.f_out = s < 2 ? fj[s + 1] : rn;
+      A.mom_in = mj[s];
+      A.mom_out = s < 2 ? mj[s + 1] : rn + 3 * fs;
+      A.alpha = a_s[s];
+      A.beta = b_s[s];
+      A.first = s == 0;
+      A.rhs_mode = 0;
+      rc = launch_stage_w<Q>(c, w, A, st);
+      if (rc) return rc;
+    }
   }
-  rc = run_moments<Q>(c, fn, amom, amom + nt, amom + 2 * nt, amom + 3 * nt, st);
-  if (rc) return rc;
-  // f^{n+1} = 1/3 f^n + 2/3 (f2 + dt L(f2)):   mu2 = 2/3 (lam3 + dt J(f2)^T lam3)
-  rc = launch_vjp<Q>(c, f2, momA, lam3, mu2, nullptr, nullptr, 2.0 / 3.0, 0.0, 0.0, dt * 2.0 / 3.0, 0, st);
-  if (rc) return rc;
-  // f2 = 3/4 f^n + 1/4 (f1 + dt L(f1)):          mu1 = 1/4 (mu2 + dt J(f1)^T mu2)
-  rc = launch_vjp<Q>(c, f1, momB, mu2, mu1, nullptr, nullptr, 0.25, 0.0, 0.0, dt * 0.25, 1, st);
-  if (rc) return rc;
-  // f1 = f^n + dt L(f^n):  lam^n = mu1 + dt J(f^n)^T mu1 + 1/3 lam3 + 3/4 mu2
-  rc = launch_vjp<Q>(c, fn, amom, mu1, lam0, lam3, mu2, 1.0, 1.0 / 3.0, 0.75, dt, 2, st);
-  if (rc) return rc;
-  hipLaunchKernelGGL(adj_reduce_kernel, dim3(1), dim3(64), 0, st, (const double*)(c->ws + c->L.adj_part),
-                     6 * c->L.ntiles_adj, dparams);
-  EVLB_HIP(hipGetLastError());
+  return EVLB_OK;
+}
+
+template <int Q>
+int run_adjoint_record(evlb_ctx* c, const double* rec, int nsteps, double* lam, const double* obs, const double* wts,
+                       double* dparams, hipStream_t st) {
+  const size_t fs = 2 * (size_t)Q * (size_t)c->L.ntot;
+  const size_t R = record_doubles(c);
+  const long long nt = c->L.ntot;
+  double* other = (double*)(c->ws + c->L.adj_lam);
+  double* cur = lam;
+  for (int j = nsteps - 1; j >= 0; --j) {
+    const double* r = rec + (size_t)j * R;
+    double* nxt = cur == lam ? other : lam;
+    const bool inj = obs && wts;
+    int rc = adjoint_core<Q>(c, r, r + 3 * fs, r + fs, r + 3 * fs + 4 * nt, r + 2 * fs, r + 3 * fs + 8 * nt, cur, nxt,
+                             dparams, st, inj ? cur : nullptr, obs, wts, j);
+    if (rc) return rc;
+    cur = nxt;
+  }
+  if (cur != lam) EVLB_HIP(hipMemcpyAsync(lam, cur, fs * sizeof(double), hipMemcpyDeviceToDevice, st));
   return EVLB_OK;
 }
 
@@ -1374,6 +1453,23 @@ int evlb_equilibrium_adjoint(evlb_ctx* ctx, const double* d_n, const double* d_u
   if (!ctx || !d_n || !d_u || !d_T || !d_lam || !d_nbar || !d_ubar || !d_Tbar) return EVLB_EINVAL;
   if (!device_matches(ctx)) return EVLB_EINVAL;
   EVLB_DISPATCH_Q(ctx->p.q, run_equilibrium_adjoint, ctx, d_n, d_u, d_T, d_lam, d_nbar, d_ubar, d_Tbar,
+                  (hipStream_t)hip_stream);
+}
+
+int64_t evlb_record_doubles(const evlb_ctx* ctx) { return ctx ? (int64_t)record_doubles(ctx) : 0; }
+
+int evlb_step_record(evlb_ctx* ctx, const double* d_f0, int32_t nsteps, double* d_rec, void* hip_stream) {
+  if (!ctx || !d_f0 || !d_rec || nsteps < 0) return EVLB_EINVAL;
+  if (!device_matches(ctx)) return EVLB_EINVAL;
+  EVLB_DISPATCH_Q(ctx->p.q, run_step_record, ctx, d_f0, nsteps, d_rec, (hipStream_t)hip_stream);
+}
+
+int evlb_adjoint_record(evlb_ctx* ctx, const double* d_rec, int32_t nsteps, double* d_lam, const double* d_obs,
+                        const double* d_w, double* d_dparams, void* hip_stream) {
+  if (!ctx || !d_rec || !d_lam || !d_dparams || nsteps < 0) return EVLB_EINVAL;
+  if (!ctx->p.adjoint || ((d_obs == nullptr) != (d_w == nullptr))) return EVLB_EINVAL;
+  if (!device_matches(ctx)) return EVLB_EINVAL;
+  EVLB_DISPATCH_Q(ctx->p.q, run_adjoint_record, ctx, d_rec, nsteps, d_lam, d_obs, d_w, d_dparams,
                   (hipStream_t)hip_stream);
 }
 

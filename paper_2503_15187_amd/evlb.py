@@ -63,6 +63,10 @@ _SIGS = {
     "evlb_moments": (ctypes.c_int, [ctypes.c_void_p] * 7),
     "evlb_adjoint_step": (ctypes.c_int, [ctypes.c_void_p] * 6),
     "evlb_equilibrium_adjoint": (ctypes.c_int, [ctypes.c_void_p] * 9),
+    "evlb_record_doubles": (ctypes.c_int64, [ctypes.c_void_p]),
+    "evlb_step_record": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                                        ctypes.c_void_p]),
+    "evlb_adjoint_record": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32] + [ctypes.c_void_p] * 5),
     "evlb_status": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32]),
     "evlb_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64), ctypes.c_void_p]),
     "evlb_destroy": (None, [ctypes.c_void_p]),
@@ -172,6 +176,21 @@ def evlb_equilibrium_adjoint(ctx, n, u, T, lam, nbar, ubar, Tbar, stream=None):
                                           _stream(stream)), "evlb_equilibrium_adjoint")
 
 
+def evlb_record_doubles(ctx):
+    return lib().evlb_record_doubles(ctx)
+
+
+def evlb_step_record(ctx, f0, nsteps, rec, stream=None):
+    _check(lib().evlb_step_record(ctx, _dptr(f0, "f0"), int(nsteps), _dptr(rec, "rec"), _stream(stream)),
+           "evlb_step_record")
+
+
+def evlb_adjoint_record(ctx, rec, nsteps, lam, obs, w, dparams, stream=None):
+    _check(lib().evlb_adjoint_record(ctx, _dptr(rec, "rec"), int(nsteps), _dptr(lam, "lam"), _dptr(obs, "obs"),
+                                     _dptr(w, "w"), _dptr(dparams, "dparams"), _stream(stream)),
+           "evlb_adjoint_record")
+
+
 def evlb_status(ctx, stream=None, clear=True):
     return lib().evlb_status(ctx, _stream(stream), 1 if clear else 0)
 
@@ -242,6 +261,23 @@ class Solver:
         lam_n = torch.empty_like(lam_np1)
         evlb_adjoint_step(self.ctx, f_n, lam_np1, lam_n, dparams, stream)
         return lam_n
+
+    def record_buffer(self, nsteps):
+        """Device buffer for evlb_step_record of nsteps steps."""
+        return torch.empty((nsteps + 1) * evlb_record_doubles(self.ctx), dtype=torch.float64, device=self.device)
+
+    def record_state(self, rec, j):
+        """View of the state f^j inside a record buffer."""
+        R = evlb_record_doubles(self.ctx)
+        return rec[j * R:j * R + 2 * self.q * self.n_tot].view(2, self.q, self.n_tot)
+
+    def step_record(self, f0, nsteps, rec, stream=None):
+        evlb_step_record(self.ctx, f0, nsteps, rec, stream)
+        return rec
+
+    def adjoint_record(self, rec, nsteps, lam, dparams, obs=None, w=None, stream=None):
+        evlb_adjoint_record(self.ctx, rec, nsteps, lam, obs, w, dparams, stream)
+        return lam
 
     def equilibrium_adjoint(self, n, u, T, lam, stream=None):
         out = torch.empty((3, self.n_tot), dtype=torch.float64, device=self.device)
