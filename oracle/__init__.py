@@ -22,7 +22,8 @@ step1d     : one TVD-RK3 time step of the reduced 1D model
 step2d     : one TVD-RK3 time step of the 2D extension
 loss       : the scalar objectives used for gradient checks
 
-Pins: every function is checked in tests/test_oracle_pins.py against
+Pins: every function is checked in tests/test_oracle_pins.py (1D) and
+tests/test_oracle2d_pins.py (2D) against
 closed forms, library routines, invariants or values printed in the paper.
 Functions without such a check say "parity unpinned" in their docstring.
 """
@@ -30,7 +31,7 @@ Functions without such a check say "parity unpinned" in their docstring.
 from .quadrature import gauss_hermite, hermite_table, equilibrium_matrix, \
     momentum_derivative_matrix
 from .model import Params
-from . import model, step1d
+from . import model, step1d, step2d
 
 __all__ = ["gauss_hermite", "hermite_table", "equilibrium_matrix",
-           "momentum_derivative_matrix", "Params", "model", "step1d"]
+           "momentum_derivative_matrix", "Params", "model", "step1d", "step2d"]

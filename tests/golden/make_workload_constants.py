@@ -13,7 +13,7 @@ import sys
 ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
 sys.path.insert(0, ROOT)
 
-from oracle import model  # noqa: E402
+from oracle import model, step2d  # noqa: E402
 from oracle.quadrature import gauss_hermite  # noqa: E402
 
 
@@ -43,6 +43,13 @@ def main():
         Q=16, dx=0.125, n_sys=512, nx_min=256, nx_max=8192, t_over_tc=[0.6, 0.95],
         n0=[0.15, 0.35], noise=0.01, steps=5000, seed=2503155,
         dt=0.2 * 0.125 / vmax[16], a_disc=a8, Tc_disc=tc8)
+
+    # 2D: attraction parameter of the cell-centre disc kernel at dx = sigma/4
+    a2d = step2d.attraction_parameter_2d(step2d.Tables2D(model.Params(Q=16, dx=0.25, dt=1.0)))
+    tc2d = model.critical_point(a2d)[1]
+    out["phase_separation_2d"] = dict(
+        Q=16, dx=0.25, nx=1024, ny=1024, T=0.75 * tc2d, n0=0.3, noise=0.01, steps=2000, seed=2503154,
+        dt=0.2 * 0.25 / vmax[16], a_disc=a2d, Tc_disc=tc2d)
 
     T5 = 0.85 * tc4
     nv5, nl5 = model.maxwell_construction(T5, a4)

@@ -52,6 +52,22 @@ def phase_separation_1d(nx=None, seed=None):
     return c, n, np.zeros(c["nx"]), np.full(c["nx"], c["T"])
 
 
+def phase_separation_2d(nx=None, ny=None, seed=None):
+    """2D uniform fluid inside the spinodal with seeded Gaussian noise,
+    n0 (1 + amp N(0, 1)), at rest, uniform temperature.  Fields have shape
+    (ny, nx).  Returns (params dict, n, ux, uy, T)."""
+    c = dict(constants()["phase_separation_2d"])
+    if nx is not None:
+        c["nx"] = nx
+    if ny is not None:
+        c["ny"] = ny
+    rng = np.random.default_rng(c["seed"] if seed is None else seed)
+    shp = (c["ny"], c["nx"])
+    n = c["n0"] * (1.0 + c["noise"] * rng.standard_normal(shp))
+    z = np.zeros(shp)
+    return c, n, z, z.copy(), np.full(shp, c["T"])
+
+
 def slab_1d(name="slab_evaporation_1d", nx=None, dx=None):
     """Liquid slab (eq:tan) centred in the periodic box, at rest, uniform
     temperature.  nx/dx may be overridden for reduced-size cases (the slab
