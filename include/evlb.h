@@ -27,6 +27,12 @@
  *    [off_s, off_s + nx[s]) with off_s = nx[0] + ... + nx[s-1]; each system
  *    is periodic on its own.
  *  - Node-field layout: d_n, d_u, d_T, d_q are [n_tot].
+ *  - dim = 2 (a fluid homogeneous in z; the paper's 1D model extended along
+ *    y, see evlb_params.dim): one periodic nx x ny system, n_tot = nx ny,
+ *    q = 16 nodes per velocity component, d_f[2][q][q][ny][nx] with plane
+ *    d q^2 + k q + l holding F (d = 0) or G (d = 1) at (p_x, p_y) =
+ *    (p_k, p_l); F = int f dp_z, G = int p_z^2/2 f dp_z.  Vector node fields
+ *    (u, q) are [2][n_tot] (x then y component).
  *  - Return value: EVLB_OK or a negative error code.  Argument errors are
  *    detected on the host before any device work is enqueued and leave all
  *    buffers untouched.  Device-detected errors (a non-positive or
@@ -45,7 +51,7 @@
 extern "C" {
 #endif
 
-#define EVLB_ABI_VERSION 1
+#define EVLB_ABI_VERSION 2
 
 enum {
   EVLB_OK = 0,
@@ -79,7 +85,15 @@ enum {
 
 typedef struct {
   int32_t abi_version;   /* must be EVLB_ABI_VERSION                         */
-  int32_t dim;           /* 1                                                */
+  int32_t dim;           /* 1, or 2 (the same model homogeneous in z only:
+                            the z-integrated kernel of eq:force over a disc,
+                            the averaged density of Sec. II A integrated
+                            along z, Shakhov and J1 reduced over p_z).
+                            dim 2 needs n_sys = 1, q = 16, gamma = 6, force
+                            EV1 or none, r_cut/dx an integer <= 24,
+                            sigma/dx <= 22, exec_mode AUTO or PER_STAGE,
+                            tile_nodes 0, adjoint 0, and
+                            dt 2 max|p_k| / dx <= 1                          */
   int32_t n_sys;         /* >= 1 independent periodic systems                */
   const int32_t* nx;     /* host [n_sys]: nodes per system, each >= 8        */
   int32_t q;             /* Gauss-Hermite order: 8, 16 or 24                 */
@@ -97,6 +111,7 @@ typedef struct {
   int32_t exec_mode;     /* EVLB_EXEC_*                                      */
   int32_t tile_nodes;    /* nodes per workgroup tile: 0 = auto, 16, 63 or 64 */
   int32_t adjoint;       /* 1: size the workspace for evlb_adjoint_step      */
+  int32_t ny;            /* dim 2: nodes along y (>= 8); ignored for dim 1   */
 } evlb_params;
 
 typedef struct evlb_ctx evlb_ctx; /* opaque, host memory */
@@ -121,7 +136,9 @@ int evlb_init(const evlb_params* params, void* d_workspace, size_t ws_bytes,
 
 /* Writes the reduced Maxwellian of the given node fields into d_f:
  * F_k = E_k(n, u, T) (Hermite expansion to order q-1), G_k = T E_k.
- * d_n, d_u, d_T: device [n_tot], read only.  d_f: device [2][q][n_tot]. */
+ * d_n, d_u, d_T: device [n_tot], read only.  d_f: device [2][q][n_tot].
+ * dim 2: d_u is [2][n_tot], F_kl = n e_k(u_x) e_l(u_y) (the product of the
+ * unit-density expansions), G_kl = T/2 F_kl. */
 int evlb_set_equilibrium(evlb_ctx* ctx, const double* d_n, const double* d_u,
                          const double* d_T, double* d_f, void* hip_stream);
 
@@ -139,7 +156,8 @@ int evlb_rhs(evlb_ctx* ctx, const double* d_f, double* d_L, void* hip_stream);
 
 /* Moments of d_f (Sec. II B): n = sum F, n u = sum p F,
  * 3/2 n T = sum (xi^2/2 F + G), q = sum xi (xi^2/2 F + G), xi = p - u.
- * Outputs device [n_tot]; d_q may be NULL. */
+ * Outputs device [n_tot]; d_q may be NULL.  dim 2: xi is the in-plane
+ * peculiar velocity and d_u, d_q are [2][n_tot]. */
 int evlb_moments(evlb_ctx* ctx, const double* d_f, double* d_n, double* d_u,
                  double* d_T, double* d_q, void* hip_stream);
 
@@ -153,8 +171,9 @@ int evlb_moments(evlb_ctx* ctx, const double* d_f, double* d_n, double* d_u,
  * below where a node sits on sigma).  All pointers are device: d_f_n,
  * d_lam_np1, d_lam_n [2][q][n_tot], d_dparams [2].  d_lam_n must not alias
  * d_lam_np1 or d_f_n.  Requires params.adjoint = 1 and force model EV1 or
- * none (EVLB_EINVAL otherwise).  The stage buffers of the workspace are
- * overwritten. */
+ * none (EVLB_EINVAL otherwise); dim 2 returns EVLB_EUNSUPPORTED, as do the
+ * record and equilibrium-adjoint calls below.  The stage buffers of the
+ * workspace are overwritten. */
 int evlb_adjoint_step(evlb_ctx* ctx, const double* d_f_n, const double* d_lam_np1,
                       double* d_lam_n, double* d_dparams, void* hip_stream);
 

@@ -6,7 +6,7 @@ import subprocess
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 LIB = os.path.join(PKG, "libevlb.so")
-SOURCES = [os.path.join(PKG, "csrc", "evlb.hip"), os.path.join(PKG, "csrc", "tables.cpp")]
+SOURCES = [os.path.join(PKG, "csrc", n) for n in ("evlb.hip", "evlb2d.hip", "tables.cpp")]
 ARCH = "gfx950"
 
 

@@ -27,6 +27,7 @@
 #include <vector>
 
 #include "../../include/evlb.h"
+#include "evlb2d.h"
 #include "tables.h"
 
 namespace {
@@ -871,6 +872,7 @@ bool is_even_multiple(double a, double dx, int* m, double tol = 1e-9) {
 int validate(const evlb_params* p) {
   if (!p) return EVLB_EINVAL;
   if (p->abi_version != EVLB_ABI_VERSION) return EVLB_EINVAL;
+  if (p->dim == 2) return evlb2d::validate(p);
   if (p->dim != 1) return EVLB_EUNSUPPORTED;
   if (p->n_sys < 1 || !p->nx) return EVLB_EINVAL;
   long long ntot = 0;
@@ -962,6 +964,7 @@ struct evlb_ctx {
   char* ws;
   int device;
   int cus;
+  evlb2d::Ctx* c2 = nullptr;  // dim = 2 path
 };
 
 namespace {
@@ -1312,6 +1315,7 @@ int evlb_validate(const evlb_params* params) { return validate(params); }
 
 size_t evlb_workspace_bytes(const evlb_params* params) {
   if (validate(params) != EVLB_OK) return 0;
+  if (params->dim == 2) return evlb2d::workspace_bytes(params);
   return make_layout(params).total;
 }
 
@@ -1320,6 +1324,24 @@ int evlb_init(const evlb_params* params, void* d_workspace, size_t ws_bytes, voi
   *out = nullptr;
   int rc = validate(params);
   if (rc) return rc;
+  if (params->dim == 2) {
+    const size_t need = evlb2d::workspace_bytes(params);
+    if (!d_workspace || ws_bytes < need || ((uintptr_t)d_workspace & 255)) return EVLB_EWORKSPACE;
+    evlb_ctx* c = new (std::nothrow) evlb_ctx();
+    if (!c) return EVLB_EINVAL;
+    c->p = *params;
+    c->nx.assign(params->nx, params->nx + 1);
+    c->p.nx = c->nx.data();
+    if (hipGetDevice(&c->device) != hipSuccess) { delete c; return EVLB_EHIP; }
+    rc = evlb2d::init(params, (char*)d_workspace, ws_bytes, &c->c2);
+    if (rc) { delete c; return rc; }
+    c->ws = (char*)d_workspace;
+    c->vel = evlb2d::velocities(c->c2);
+    c->L.ntot = evlb2d::node_count(c->c2);
+    c->dp.status = evlb2d::status_word(c->c2);
+    *out = c;
+    return EVLB_OK;
+  }
   const Layout L = make_layout(params);
   if (!d_workspace || ws_bytes < L.total || ((uintptr_t)d_workspace & 255)) return EVLB_EWORKSPACE;
   evlb_ctx* c = new (std::nothrow) evlb_ctx();
@@ -1416,6 +1438,7 @@ int evlb_set_equilibrium(evlb_ctx* ctx, const double* d_n, const double* d_u, co
                          void* hip_stream) {
   if (!ctx || !d_n || !d_u || !d_T || !d_f) return EVLB_EINVAL;
   if (!device_matches(ctx)) return EVLB_EINVAL;
+  if (ctx->c2) return evlb2d::set_equilibrium(ctx->c2, d_n, d_u, d_T, d_f, (hipStream_t)hip_stream);
   EVLB_DISPATCH_Q(ctx->p.q, run_equilibrium, ctx, d_n, d_u, d_T, d_f, (hipStream_t)hip_stream);
 }
 
@@ -1423,12 +1446,14 @@ int evlb_step(evlb_ctx* ctx, double* d_f, int32_t nsteps, void* hip_stream) {
   if (!ctx || !d_f || nsteps < 0) return EVLB_EINVAL;
   if (!device_matches(ctx)) return EVLB_EINVAL;
   if (nsteps == 0) return EVLB_OK;
+  if (ctx->c2) return evlb2d::step(ctx->c2, d_f, nsteps, (hipStream_t)hip_stream);
   EVLB_DISPATCH_Q(ctx->p.q, run_step, ctx, d_f, nsteps, (hipStream_t)hip_stream);
 }
 
 int evlb_rhs(evlb_ctx* ctx, const double* d_f, double* d_L, void* hip_stream) {
   if (!ctx || !d_f || !d_L || d_f == d_L) return EVLB_EINVAL;
   if (!device_matches(ctx)) return EVLB_EINVAL;
+  if (ctx->c2) return evlb2d::rhs(ctx->c2, d_f, d_L, (hipStream_t)hip_stream);
   EVLB_DISPATCH_Q(ctx->p.q, run_rhs, ctx, d_f, d_L, (hipStream_t)hip_stream);
 }
 
@@ -1436,12 +1461,14 @@ int evlb_moments(evlb_ctx* ctx, const double* d_f, double* d_n, double* d_u, dou
                  void* hip_stream) {
   if (!ctx || !d_f || !d_n || !d_u || !d_T) return EVLB_EINVAL;
   if (!device_matches(ctx)) return EVLB_EINVAL;
+  if (ctx->c2) return evlb2d::moments(ctx->c2, d_f, d_n, d_u, d_T, d_q, (hipStream_t)hip_stream);
   EVLB_DISPATCH_Q(ctx->p.q, run_moments, ctx, d_f, d_n, d_u, d_T, d_q, (hipStream_t)hip_stream);
 }
 
 int evlb_adjoint_step(evlb_ctx* ctx, const double* d_f_n, const double* d_lam_np1, double* d_lam_n,
                       double* d_dparams, void* hip_stream) {
   if (!ctx || !d_f_n || !d_lam_np1 || !d_lam_n || !d_dparams) return EVLB_EINVAL;
+  if (ctx->c2) return EVLB_EUNSUPPORTED;
   if (!ctx->p.adjoint) return EVLB_EINVAL;
   if (d_lam_n == d_lam_np1 || (const double*)d_lam_n == d_f_n) return EVLB_EINVAL;
   if (!device_matches(ctx)) return EVLB_EINVAL;
@@ -1451,15 +1478,17 @@ int evlb_adjoint_step(evlb_ctx* ctx, const double* d_f_n, const double* d_lam_np
 int evlb_equilibrium_adjoint(evlb_ctx* ctx, const double* d_n, const double* d_u, const double* d_T,
                              const double* d_lam, double* d_nbar, double* d_ubar, double* d_Tbar, void* hip_stream) {
   if (!ctx || !d_n || !d_u || !d_T || !d_lam || !d_nbar || !d_ubar || !d_Tbar) return EVLB_EINVAL;
+  if (ctx->c2) return EVLB_EUNSUPPORTED;
   if (!device_matches(ctx)) return EVLB_EINVAL;
   EVLB_DISPATCH_Q(ctx->p.q, run_equilibrium_adjoint, ctx, d_n, d_u, d_T, d_lam, d_nbar, d_ubar, d_Tbar,
                   (hipStream_t)hip_stream);
 }
 
-int64_t evlb_record_doubles(const evlb_ctx* ctx) { return ctx ? (int64_t)record_doubles(ctx) : 0; }
+int64_t evlb_record_doubles(const evlb_ctx* ctx) { return ctx && !ctx->c2 ? (int64_t)record_doubles(ctx) : 0; }
 
 int evlb_step_record(evlb_ctx* ctx, const double* d_f0, int32_t nsteps, double* d_rec, void* hip_stream) {
   if (!ctx || !d_f0 || !d_rec || nsteps < 0) return EVLB_EINVAL;
+  if (ctx->c2) return EVLB_EUNSUPPORTED;
   if (!device_matches(ctx)) return EVLB_EINVAL;
   EVLB_DISPATCH_Q(ctx->p.q, run_step_record, ctx, d_f0, nsteps, d_rec, (hipStream_t)hip_stream);
 }
@@ -1467,6 +1496,7 @@ int evlb_step_record(evlb_ctx* ctx, const double* d_f0, int32_t nsteps, double* 
 int evlb_adjoint_record(evlb_ctx* ctx, const double* d_rec, int32_t nsteps, double* d_lam, const double* d_obs,
                         const double* d_w, double* d_dparams, void* hip_stream) {
   if (!ctx || !d_rec || !d_lam || !d_dparams || nsteps < 0) return EVLB_EINVAL;
+  if (ctx->c2) return EVLB_EUNSUPPORTED;
   if (!ctx->p.adjoint || ((d_obs == nullptr) != (d_w == nullptr))) return EVLB_EINVAL;
   if (!device_matches(ctx)) return EVLB_EINVAL;
   EVLB_DISPATCH_Q(ctx->p.q, run_adjoint_record, ctx, d_rec, nsteps, d_lam, d_obs, d_w, d_dparams,
@@ -1491,7 +1521,10 @@ int evlb_info(const evlb_ctx* ctx, int64_t* n_tot, double* h_velocities) {
   return EVLB_OK;
 }
 
-void evlb_destroy(evlb_ctx* ctx) { delete ctx; }
+void evlb_destroy(evlb_ctx* ctx) {
+  if (ctx && ctx->c2) evlb2d::destroy(ctx->c2);
+  delete ctx;
+}
 
 const char* evlb_strerror(int code) {
   switch (code) {

@@ -1,0 +1,807 @@
+// 2D extension of the EV-FDLB step for MI355X (gfx950): a fluid homogeneous
+// in z, F(x, y, p_x, p_y) = int f dp_z and G = int p_z^2/2 f dp_z on the
+// tensor-product Gauss-Hermite set (p_k, p_l), k, l < 16.  The paper solves
+// the 1D model and names more dimensions as the next goal (conclusions); the
+// same ingredients reduced over p_z give the right-hand side
+//   L = -p . grad f - F . grad_p f - nu (f - f^S) + J1
+// with the Shakhov f^S (Sec. II B) and J1 (eq:J1) reduced over p_z, the
+// mean-field force of eq:force integrated along z, and the averaged density
+// of Sec. II A integrated along z.
+//
+// State d_f[2][16][16][ny][nx] (plane d*256 + k*16 + l, node fastest).  One
+// TVD-RK3 stage is three kernels:
+//   fields_kernel  32 x 8 nodes per workgroup, density tile with the force
+//                  radius as halo in LDS: disc-averaged density, contact value
+//                  (eq:carnstar), force (antisymmetric cell pairs), transport
+//                  (eq:viscosity, eq:tau, eq:prandtl), 4th-order central
+//                  gradients of X = n^2 chi T, T and u along x and y.
+//   adv_kernel     one velocity plane x a 64 x 16 tile per workgroup: the tile
+//                  and a 3-node halo in LDS, every WENO-5 face computed once,
+//                  W = a f^n + b f^(s-1) + c Adv(f^(s-1)).
+//   vel_kernel     16 nodes per wavefront, lanes = (node, group g of four p_x
+//                  rows): d/dp_x as (Dp x I) on the f64 MFMA (the node's 16 x 16
+//                  velocity matrix is the B operand), d/dp_y as (I x Dp) on the
+//                  VALU, Hermite equilibrium, Shakhov and J1 terms,
+//                  f^(s) = W + c R, and the velocity moments of f^(s).
+#include "evlb2d.h"
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <new>
+
+#include "tables.h"
+
+namespace evlb2d {
+namespace {
+
+constexpr int Q = 16;
+constexpr int V = Q * Q;
+constexpr int HMAX = 24;  // max halo of the fields tile (force radius / averaging disc + 2)
+
+enum {
+  F_N, F_UX, F_UY, F_T, F_SQX, F_SQY, F_NU, F_PRE, F_FX, F_FY,
+  F_AX, F_AY, F_BX, F_BY, F_UXX, F_UXY, F_UYX, F_UYY, NF
+};
+
+struct Dev {
+  int nx, ny;
+  long long ntot;
+  double inv_dx;
+  double b;      // 2 pi sigma^3 / 3
+  double eta_c;  // pi sigma^3 / 6
+  double mu0c;   // 5 / (16 sigma^2 sqrt(pi))
+  double weno_eps, g_ext;
+  int force_model, term_mask;
+  int navg, npair, halo;
+  int* status;
+};
+
+__device__ __forceinline__ int wrap(int i, int n) {
+  const int r = i % n;
+  return r < 0 ? r + n : r;
+}
+
+// WENO-5 (Jiang & Shu) face value from the upwind-ordered v0..v4; the three
+// nonlinear weights over a common denominator (one division).
+__device__ __forceinline__ double weno5(double v0, double v1, double v2, double v3, double v4, double eps) {
+  const double q0 = (2.0 * v0 - 7.0 * v1 + 11.0 * v2) * (1.0 / 6.0);
+  const double q1 = (-v1 + 5.0 * v2 + 2.0 * v3) * (1.0 / 6.0);
+  const double q2 = (2.0 * v2 + 5.0 * v3 - v4) * (1.0 / 6.0);
+  const double c0 = v0 - 2.0 * v1 + v2, e0 = v0 - 4.0 * v1 + 3.0 * v2;
+  const double c1 = v1 - 2.0 * v2 + v3, e1 = v1 - v3;
+  const double c2 = v2 - 2.0 * v3 + v4, e2 = 3.0 * v2 - 4.0 * v3 + v4;
+  const double b0 = (13.0 / 12.0) * c0 * c0 + 0.25 * e0 * e0;
+  const double b1 = (13.0 / 12.0) * c1 * c1 + 0.25 * e1 * e1;
+  const double b2 = (13.0 / 12.0) * c2 * c2 + 0.25 * e2 * e2;
+  double t0 = eps + b0; t0 *= t0;
+  double t1 = eps + b1; t1 *= t1;
+  double t2 = eps + b2; t2 *= t2;
+  const double w0 = 0.1 * t1 * t2, w1 = 0.6 * t0 * t2, w2 = 0.3 * t0 * t1;
+  return (w0 * q0 + w1 * q1 + w2 * q2) / (w0 + w1 + w2);
+}
+
+// Raw velocity sums of one node -> n, u, T, q (Sec. II B moments with the
+// reduced G carrying the p_z energy):
+//   3/2 n T = sum (|xi|^2/2 F + G),  q = sum xi (|xi|^2/2 F + G).
+struct Raw {
+  double n, jx, jy, pxx, pxy, pyy, rx, ry, g0, hx, hy;
+};
+
+__device__ __forceinline__ void finish_moments(const Raw& m, double* out6, long long N, long long node,
+                                               int* status) {
+  const double n = m.n;
+  const double ux = m.jx / n, uy = m.jy / n;
+  const double u2 = ux * ux + uy * uy;
+  const double tr = m.pxx + m.pyy;
+  const double T = (2.0 / 3.0) * (0.5 * tr + m.g0 - 0.5 * n * u2) / n;
+  const double qx = 0.5 * (m.rx - 2.0 * (ux * m.pxx + uy * m.pxy) - ux * tr + 2.0 * n * ux * u2) + (m.hx - ux * m.g0);
+  const double qy = 0.5 * (m.ry - 2.0 * (ux * m.pxy + uy * m.pyy) - uy * tr + 2.0 * n * uy * u2) + (m.hy - uy * m.g0);
+  out6[node] = n;
+  out6[N + node] = ux;
+  out6[2 * N + node] = uy;
+  out6[3 * N + node] = T;
+  out6[4 * N + node] = qx;
+  out6[5 * N + node] = qy;
+  if (!(n > 0.0) || !(T > 0.0) || !isfinite(n) || !isfinite(T) || !isfinite(ux) || !isfinite(uy) ||
+      !isfinite(qx) || !isfinite(qy))
+    status[0] = 1;
+}
+
+// ---------------------------------------------------------------------------
+// moments of a state (first stage of a step, evlb_moments)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void moments_kernel(Dev D, const double* __restrict__ f, double* __restrict__ out6,
+                                                      const double* __restrict__ vel) {
+  const long long node = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (node >= D.ntot) return;
+  const long long N = D.ntot;
+  Raw m{0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll 1
+  for (int k = 0; k < Q; ++k) {
+    const double pk = vel[k];
+#pragma unroll 4
+    for (int l = 0; l < Q; ++l) {
+      const double pl = vel[l];
+      const double F = f[(long long)(k * Q + l) * N + node];
+      const double G = f[(long long)(V + k * Q + l) * N + node];
+      const double p2 = pk * pk + pl * pl;
+      m.n += F;
+      m.jx += pk * F;
+      m.jy += pl * F;
+      m.pxx += pk * pk * F;
+      m.pxy += pk * pl * F;
+      m.pyy += pl * pl * F;
+      m.rx += pk * p2 * F;
+      m.ry += pl * p2 * F;
+      m.g0 += G;
+      m.hx += pk * G;
+      m.hy += pl * G;
+    }
+  }
+  finish_moments(m, out6, N, node, D.status);
+}
+
+// Hermite equilibrium of one velocity component at unit density:
+// a_0 = 1, a_1 = u, a_{m+1} = u a_m + m (T - 1) a_{m-1};  e_k = sum_m meq[k][m] a_m.
+__device__ __forceinline__ void hermite_coeffs(double u, double T, double* a) {
+  a[0] = 1.0;
+  a[1] = u;
+#pragma unroll
+  for (int m = 1; m < Q - 1; ++m) a[m + 1] = u * a[m] + (double)m * (T - 1.0) * a[m - 1];
+}
+
+__global__ __launch_bounds__(256) void equilibrium_kernel(Dev D, const double* __restrict__ n_in,
+                                                          const double* __restrict__ u_in,
+                                                          const double* __restrict__ T_in, double* __restrict__ f,
+                                                          const double* __restrict__ meq) {
+  const long long node = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (node >= D.ntot) return;
+  const long long N = D.ntot;
+  const double n = n_in[node], ux = u_in[node], uy = u_in[N + node], T = T_in[node];
+  double ax[Q], ay[Q], ey[Q];
+  hermite_coeffs(ux, T, ax);
+  hermite_coeffs(uy, T, ay);
+#pragma unroll
+  for (int l = 0; l < Q; ++l) {
+    double s = 0.0;
+#pragma unroll
+    for (int m = 0; m < Q; ++m) s += meq[l * Q + m] * ay[m];
+    ey[l] = s;
+  }
+#pragma unroll 1
+  for (int k = 0; k < Q; ++k) {
+    double ex = 0.0;
+#pragma unroll
+    for (int m = 0; m < Q; ++m) ex += meq[k * Q + m] * ax[m];
+    const double nex = n * ex;
+#pragma unroll
+    for (int l = 0; l < Q; ++l) {
+      const double E = nex * ey[l];
+      f[(long long)(k * Q + l) * N + node] = E;
+      f[(long long)(V + k * Q + l) * N + node] = 0.5 * T * E;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// node fields
+// ---------------------------------------------------------------------------
+constexpr int FTX = 32, FTY = 8, FNT = FTX * FTY;
+constexpr int GX = FTX + 4, GY = FTY + 4;  // tile +-2 (gradient stencil)
+
+__global__ __launch_bounds__(FNT) void fields_kernel(Dev D, const double* __restrict__ mom, double* __restrict__ fld,
+                                                     const int* __restrict__ avg_ofs,
+                                                     const double* __restrict__ avg_w,
+                                                     const int* __restrict__ pair_ofs,
+                                                     const double* __restrict__ pair_cx,
+                                                     const double* __restrict__ pair_cy) {
+  extern __shared__ double sm[];
+  const int H = D.halo, PX = FTX + 2 * H, PY = FTY + 2 * H;
+  double* sn = sm;             // [PY][PX] density, node (x0 - H + c, y0 - H + r)
+  double* sX = sn + PX * PY;   // [GY][GX] node (x0 - 2 + c, y0 - 2 + r)
+  double* sT = sX + GX * GY;
+  double* sux = sT + GX * GY;
+  double* suy = sux + GX * GY;
+  double* sC = suy + GX * GY;
+  const int tid = threadIdx.x;
+  const int x0 = blockIdx.x * FTX, y0 = blockIdx.y * FTY;
+  const long long N = D.ntot;
+  for (int i = tid; i < PX * PY; i += FNT) {
+    const int r = i / PX, c = i - r * PX;
+    sn[i] = mom[(long long)wrap(y0 - H + r, D.ny) * D.nx + wrap(x0 - H + c, D.nx)];
+  }
+  for (int i = tid; i < GX * GY; i += FNT) {
+    const int r = i / GX, c = i - r * GX;
+    const long long node = (long long)wrap(y0 - 2 + r, D.ny) * D.nx + wrap(x0 - 2 + c, D.nx);
+    sux[i] = mom[N + node];
+    suy[i] = mom[2 * N + node];
+    sT[i] = mom[3 * N + node];
+  }
+  __syncthreads();
+  // averaged density over the disc, contact value, X on the tile +-2
+  for (int i = tid; i < GX * GY; i += FNT) {
+    const int r = i / GX, c = i - r * GX;
+    const int ctr = (r - 2 + H) * PX + (c - 2 + H);
+    double s0 = 0.0, s1 = 0.0;
+    int t = 0;
+    for (; t + 1 < D.navg; t += 2) {
+      s0 += avg_w[t] * sn[ctr + avg_ofs[t]];
+      s1 += avg_w[t + 1] * sn[ctr + avg_ofs[t + 1]];
+    }
+    if (t < D.navg) s0 += avg_w[t] * sn[ctr + avg_ofs[t]];
+    const double eta = D.eta_c * (s0 + s1);
+    const double om = 1.0 - eta;
+    const double chi = (2.0 - eta) / (2.0 * om * om * om);
+    const double n = sn[ctr];
+    sC[i] = chi;
+    sX[i] = n * n * chi * sT[i];
+  }
+  __syncthreads();
+
+  const int tx = tid % FTX, ty = tid / FTX;
+  const int x = x0 + tx, y = y0 + ty;
+  if (x >= D.nx || y >= D.ny) return;
+  const long long node = (long long)y * D.nx + x;
+  const int g = (ty + 2) * GX + (tx + 2);
+  const int ctr = (ty + H) * PX + (tx + H);
+  const double n = sn[ctr], T = sT[g], ux = sux[g], uy = suy[g], chi = sC[g];
+  double Fx = D.g_ext, Fy = 0.0;
+  if (D.force_model == EVLB_FORCE_EV1) {
+    double ax0 = 0.0, ax1 = 0.0, ay0 = 0.0, ay1 = 0.0;
+    int t = 0;
+    for (; t + 1 < D.npair; t += 2) {
+      const double d0 = sn[ctr + pair_ofs[t]] - sn[ctr - pair_ofs[t]];
+      const double d1 = sn[ctr + pair_ofs[t + 1]] - sn[ctr - pair_ofs[t + 1]];
+      ax0 += pair_cx[t] * d0;
+      ay0 += pair_cy[t] * d0;
+      ax1 += pair_cx[t + 1] * d1;
+      ay1 += pair_cy[t + 1] * d1;
+    }
+    if (t < D.npair) {
+      const double d0 = sn[ctr + pair_ofs[t]] - sn[ctr - pair_ofs[t]];
+      ax0 += pair_cx[t] * d0;
+      ay0 += pair_cy[t] * d0;
+    }
+    Fx += ax0 + ax1;
+    Fy = ay0 + ay1;
+  }
+  const double c12 = D.inv_dx * (1.0 / 12.0);
+  const double X = sX[g];
+  const double Ax = (sX[g - 2] - 8.0 * sX[g - 1] + 8.0 * sX[g + 1] - sX[g + 2]) * c12 / X;
+  const double Ay = (sX[g - 2 * GX] - 8.0 * sX[g - GX] + 8.0 * sX[g + GX] - sX[g + 2 * GX]) * c12 / X;
+  const double Bx = (sT[g - 2] - 8.0 * sT[g - 1] + 8.0 * sT[g + 1] - sT[g + 2]) * c12 / T;
+  const double By = (sT[g - 2 * GX] - 8.0 * sT[g - GX] + 8.0 * sT[g + GX] - sT[g + 2 * GX]) * c12 / T;
+  const double Uxx = (sux[g - 2] - 8.0 * sux[g - 1] + 8.0 * sux[g + 1] - sux[g + 2]) * c12;
+  const double Uxy = (suy[g - 2] - 8.0 * suy[g - 1] + 8.0 * suy[g + 1] - suy[g + 2]) * c12;
+  const double Uyx = (sux[g - 2 * GX] - 8.0 * sux[g - GX] + 8.0 * sux[g + GX] - sux[g + 2 * GX]) * c12;
+  const double Uyy = (suy[g - 2 * GX] - 8.0 * suy[g - GX] + 8.0 * suy[g + GX] - suy[g + 2 * GX]) * c12;
+  const double bn = D.b * n;
+  const double yv = bn * chi;
+  const double k12 = 0.16 * (1.0 + 12.0 / M_PI);
+  const double k32 = 0.36 * (1.0 + 32.0 / (9.0 * M_PI));
+  const double mu = D.mu0c * sqrt(T) * (1.0 / chi + 0.8 * bn + k12 * bn * bn * chi);
+  const double nu = chi * n * T * (1.0 + 0.4 * yv) / mu;
+  const double Pr = (2.0 / 3.0) * (1.0 + 0.6 * yv) * (1.0 + 0.8 * yv + k12 * yv * yv) /
+                    ((1.0 + 0.4 * yv) * (1.0 + 1.2 * yv + k32 * yv * yv));
+  const double s = (1.0 - Pr) / (5.0 * n * T * T);
+  const double vals[NF] = {n, ux, uy, T, s * mom[4 * N + node], s * mom[5 * N + node], nu, -bn * chi, Fx, Fy,
+                           Ax, Ay, Bx, By, Uxx, Uxy, Uyx, Uyy};
+#pragma unroll
+  for (int i = 0; i < NF; ++i) fld[i * N + node] = vals[i];
+}
+
+// ---------------------------------------------------------------------------
+// advection: one velocity plane x one 64 x 16 tile
+// ---------------------------------------------------------------------------
+constexpr int ATX = 64, ATY = 16, ANT = 256;
+constexpr int APX = ATX + 6, APY = ATY + 6;
+constexpr int NXF = ATY * (ATX + 1), NYF = (ATY + 1) * ATX;
+
+struct AdvArgs {
+  const double* fs;  // f^(s-1)
+  const double* f0;  // f^n
+  double* W;         // a f^n + b f^(s-1) + c Adv(f^(s-1)); may alias f0
+  double a, b, c;
+  int first;         // f0 == fs
+};
+
+__global__ __launch_bounds__(ANT) void adv_kernel(Dev D, AdvArgs A, const double* __restrict__ vel) {
+  __shared__ double sf[APY * APX];  // node (x0 - 3 + c, y0 - 3 + r)
+  __shared__ double xf[NXF];        // face x0 + fx - 1/2 of row r: [r][fx]
+  __shared__ double yf[NYF];        // face y0 + fy - 1/2 of column c: [fy][c]
+  const int ntx = (D.nx + ATX - 1) / ATX, nty = (D.ny + ATY - 1) / ATY;
+  // consecutive workgroups go to different XCDs; hand each XCD a contiguous
+  // range of tiles so that the y-halo rows of a tile row meet in its L2
+  unsigned b = blockIdx.x;
+  const unsigned nb = gridDim.x;
+  if ((nb & 7u) == 0) b = (b & 7u) * (nb >> 3) + (b >> 3);
+  const int tx = (int)(b % (unsigned)ntx);
+  b /= (unsigned)ntx;
+  const int ty = (int)(b % (unsigned)nty);
+  const int plane = (int)(b / (unsigned)nty);
+  const int v = plane % V, k = v / Q, l = v - k * Q;
+  const double px = vel[k], py = vel[l];
+  const long long base = (long long)plane * D.ntot;
+  const double* fs = A.fs + base;
+  const int x0 = tx * ATX, y0 = ty * ATY;
+  const int tid = threadIdx.x;
+  const bool adv = (D.term_mask & EVLB_TERM_ADV) != 0;
+  if (adv) {
+    for (int i = tid; i < APX * APY; i += ANT) {
+      const int r = i / APX, c = i - r * APX;
+      sf[i] = fs[(long long)wrap(y0 - 3 + r, D.ny) * D.nx + wrap(x0 - 3 + c, D.nx)];
+    }
+    __syncthreads();
+    const bool posx = px > 0.0, posy = py > 0.0;
+    for (int t = tid; t < NXF + NYF; t += ANT) {
+      if (t < NXF) {
+        // face between nodes x0 + fx - 1 and x0 + fx; upwind by the sign of p_x
+        const int r = t / (ATX + 1), fx = t - r * (ATX + 1);
+        const double* row = sf + (r + 3) * APX;
+        const int c0 = posx ? fx : fx + 5;
+        const int st = posx ? 1 : -1;
+        xf[t] = weno5(row[c0], row[c0 + st], row[c0 + 2 * st], row[c0 + 3 * st], row[c0 + 4 * st], D.weno_eps);
+      } else {
+        const int u = t - NXF;
+        const int fy = u / ATX, c = u - fy * ATX;
+        const double* col = sf + c + 3;
+        const int r0 = posy ? fy : fy + 5;
+        const int st = posy ? APX : -APX;
+        const int o = r0 * APX;
+        yf[u] = weno5(col[o], col[o + st], col[o + 2 * st], col[o + 3 * st], col[o + 4 * st], D.weno_eps);
+      }
+    }
+    __syncthreads();
+  }
+  for (int o = tid; o < ATX * ATY; o += ANT) {
+    const int r = o / ATX, c = o - r * ATX;
+    const int x = x0 + c, y = y0 + r;
+    if (x >= D.nx || y >= D.ny) continue;
+    const long long node = (long long)y * D.nx + x;
+    double fv, av = 0.0;
+    if (adv) {
+      fv = sf[(r + 3) * APX + c + 3];
+      av = -(px * (xf[r * (ATX + 1) + c + 1] - xf[r * (ATX + 1) + c]) +
+             py * (yf[(r + 1) * ATX + c] - yf[r * ATX + c])) * D.inv_dx;
+    } else {
+      fv = fs[node];
+    }
+    const double f0v = A.first ? fv : A.f0[base + node];
+    A.W[base + node] = A.a * f0v + A.b * fv + A.c * av;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// velocity space: 16 nodes per wavefront
+// ---------------------------------------------------------------------------
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+struct VelArgs {
+  const double* fs;   // f^(s-1)
+  double* W;          // in: advection part; out: f^(s) = W + c R(f^(s-1))
+  const double* fld;  // [NF][ntot]
+  double* mom;        // [6][ntot] moments of f^(s) (want_mom)
+  double c;
+  int want_mom;
+};
+
+// Lane (nd, g) = (lane & 15, lane >> 4) owns node x = x_w + nd and the velocity
+// rows k = 4 g + j, j < 4, for every l: M[j][l] = f[k][l] (64 values).
+// (Dp x I) M on the MFMA: D = sum_b A_b B_b over b < 4 with A_b[i][c] =
+// Dp[i][4c + b] (lane holds Dp[nd][4g + b]) and B_b[c][node] = M_node[4c + b][l]
+// (lane holds M[b][l]); the 16 x 16 result D[k][node] comes back as
+// D[4g + j][nd] in element j of the lane's accumulator, the same rows the lane
+// owns.  (I x Dp) M contracts over l, which the lane holds whole: VALU.
+__global__ __launch_bounds__(256) void vel_kernel(Dev D, VelArgs A, const double* __restrict__ vel,
+                                                  const double* __restrict__ meq,
+                                                  const double* __restrict__ dpm) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int nd = lane & 15, g = lane >> 4;
+  const int nseg = (D.nx + 63) >> 6;
+  const int y = blockIdx.x / nseg, seg = blockIdx.x - y * nseg;
+  const int x = seg * 64 + wave * 16 + nd;
+  const bool valid = x < D.nx;
+  const long long N = D.ntot;
+  // lanes past the row end work on the last node and store nothing
+  const long long node = (long long)y * D.nx + (valid ? x : D.nx - 1);
+
+  double fl[NF];
+#pragma unroll
+  for (int i = 0; i < NF; ++i) fl[i] = A.fld[i * N + node];
+  const double n = fl[F_N], ux = fl[F_UX], uy = fl[F_UY], T = fl[F_T];
+  const double invT = 1.0 / T;
+  const double div = fl[F_UXX] + fl[F_UYY];
+
+  // unit-density Hermite equilibria e_k(u_x) (own rows) and e_l(u_y) (all)
+  double ex[4] = {0.0, 0.0, 0.0, 0.0}, ey[Q];
+  {
+    double a[Q];
+    hermite_coeffs(uy, T, a);
+#pragma unroll
+    for (int l = 0; l < Q; ++l) {
+      double s = 0.0;
+#pragma unroll
+      for (int m = 0; m < Q; ++m) s += meq[l * Q + m] * a[m];
+      ey[l] = s;
+    }
+    hermite_coeffs(ux, T, a);
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+      double s = 0.0;
+#pragma unroll
+      for (int m = 0; m < Q; ++m) s += meq[k * Q + m] * a[m];
+      if ((k >> 2) == g) ex[k & 3] = s;
+    }
+  }
+  double pkv[4], aop[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    pkv[j] = vel[4 * g + j];
+    aop[j] = dpm[nd * Q + 4 * g + j];
+  }
+  const bool frc = (D.term_mask & EVLB_TERM_FORCE) != 0;
+  const bool j0 = (D.term_mask & EVLB_TERM_J0) != 0;
+  const bool j1 = (D.term_mask & EVLB_TERM_J1) != 0;
+
+  Raw m{0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll 1
+  for (int d = 0; d < 2; ++d) {
+    // Opaque copies: everything the F and G passes share is recomputed in
+    // each pass instead of being hoisted out of the loop, which would hold
+    // 64 equilibria, 256 Dp entries, ... live across both passes.
+    double n_d = n, ux_d = ux, uy_d = uy, it_d = invT;
+    const double* dp = dpm;
+    const double* vl = vel;
+    asm volatile("" : "+v"(n_d), "+v"(ux_d), "+v"(uy_d), "+v"(it_d));
+    asm volatile("" : "+s"(dp), "+s"(vl));
+    const double* src = A.fs + (long long)d * V * N + node;
+    double* wio = A.W + (long long)d * V * N + node;
+    double M[4][Q];
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int l = 0; l < Q; ++l) M[j][l] = src[(long long)((4 * g + j) * Q + l) * N];
+    // F: F^S = E [1 + s(xi.q)(th - 4)], J1F; G: T/2 E, th - 2 (reduction over p_z)
+    const double tf = d == 0 ? 1.0 : 0.5 * T;
+    const double th0 = d == 0 ? 4.0 : 2.0;
+    // fully unrolled: every M[j][l] index is static, M stays in registers
+#pragma unroll
+    for (int l = 0; l < Q; ++l) {
+      dbl4 acc = {0.0, 0.0, 0.0, 0.0};
+      if (frc) {
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(aop[0], M[0][l], acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(aop[1], M[1][l], acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(aop[2], M[2][l], acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(aop[3], M[3][l], acc, 0, 0, 0);
+      }
+      const double pl = vl[l];
+      const double xy = pl - uy_d;
+      const double eyl = ey[l];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const double f = M[j][l];
+        const double pk = pkv[j];
+        const double xx = pk - ux_d;
+        const double th = (xx * xx + xy * xy) * it_d;
+        const double E = n_d * ex[j] * eyl;
+        double R = 0.0;
+        if (frc) {
+          double d0 = 0.0, d1 = 0.0;
+#pragma unroll
+          for (int l2 = 0; l2 < Q; l2 += 2) {
+            d0 += dp[l * Q + l2] * M[j][l2];
+            d1 += dp[l * Q + l2 + 1] * M[j][l2 + 1];
+          }
+          R -= fl[F_FX] * acc[j] + fl[F_FY] * (d0 + d1);
+        }
+        if (j0) {
+          const double fS = tf * E * (1.0 + (xx * fl[F_SQX] + xy * fl[F_SQY]) * (th - th0));
+          R -= fl[F_NU] * (f - fS);
+        }
+        if (j1) {
+          const double xA = xx * fl[F_AX] + xy * fl[F_AY];
+          const double xB = xx * fl[F_BX] + xy * fl[F_BY];
+          const double xxu = (xx * xx * fl[F_UXX] + xx * xy * fl[F_UXY] + xy * xx * fl[F_UYX] +
+                              xy * xy * fl[F_UYY]) * it_d;
+          R += fl[F_PRE] * tf * E * (xA + 0.3 * (th - th0) * xB + 0.4 * (xxu + 0.5 * (th - th0) * div));
+        }
+        const long long o = (long long)((4 * g + j) * Q + l) * N;
+        const double out = wio[o] + A.c * R;
+        if (valid) wio[o] = out;
+        if (d == 0) {
+          const double p2 = pk * pk + pl * pl;
+          m.n += out;
+          m.jx += pk * out;
+          m.jy += pl * out;
+          m.pxx += pk * pk * out;
+          m.pxy += pk * pl * out;
+          m.pyy += pl * pl * out;
+          m.rx += pk * p2 * out;
+          m.ry += pl * p2 * out;
+        } else {
+          m.g0 += out;
+          m.hx += pk * out;
+          m.hy += pl * out;
+        }
+      }
+      // keep the scheduler from hoisting the W loads of later columns
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+  if (!A.want_mom) return;
+  // the four lanes of a node (g = 0..3) hold partial sums over their rows
+#define EVLB2D_REDUCE(v) v += __shfl_xor(v, 16); v += __shfl_xor(v, 32)
+  EVLB2D_REDUCE(m.n); EVLB2D_REDUCE(m.jx); EVLB2D_REDUCE(m.jy); EVLB2D_REDUCE(m.pxx);
+  EVLB2D_REDUCE(m.pxy); EVLB2D_REDUCE(m.pyy); EVLB2D_REDUCE(m.rx); EVLB2D_REDUCE(m.ry);
+  EVLB2D_REDUCE(m.g0); EVLB2D_REDUCE(m.hx); EVLB2D_REDUCE(m.hy);
+#undef EVLB2D_REDUCE
+  if (valid && g == 0) finish_moments(m, A.mom, N, node, D.status);
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct Layout {
+  size_t tab_d, tab_i, f1, f2, mom, fld, status, total;
+  int navg, npair, halo;
+};
+
+bool is_integer_multiple(double a, double dx, int* m) {
+  const double r = a / dx;
+  const long long k = llround(r);
+  if (k <= 0 || std::fabs(r - (double)k) > 1e-9 * r) return false;
+  *m = (int)k;
+  return true;
+}
+
+Layout make_layout(const evlb_params* p, const evlb::DiscTables& t) {
+  Layout L{};
+  const long long N = (long long)p->nx[0] * p->ny;
+  L.navg = (int)t.avg_w.size();
+  L.npair = (int)t.pair_cx.size();
+  L.halo = t.pair_reach > t.avg_reach + 2 ? t.pair_reach : t.avg_reach + 2;
+  size_t off = 0;
+  L.tab_d = off;
+  off += align256(sizeof(double) * (size_t)(Q + 2 * Q * Q + L.navg + 2 * (L.npair > 0 ? L.npair : 1)));
+  L.tab_i = off;
+  off += align256(sizeof(int) * (size_t)(L.navg + (L.npair > 0 ? L.npair : 1)));
+  const size_t fbytes = align256(sizeof(double) * 2 * (size_t)V * (size_t)N);
+  L.f1 = off; off += fbytes;
+  L.f2 = off; off += fbytes;
+  L.mom = off; off += align256(sizeof(double) * 6 * (size_t)N);
+  L.fld = off; off += align256(sizeof(double) * NF * (size_t)N);
+  L.status = off; off += 256;
+  L.total = off;
+  return L;
+}
+
+void disc_tables(const evlb_params* p, evlb::DiscTables& t) {
+  evlb::build_disc_tables(p->dx, p->sigma, p->phi_sigma, p->r_cut, p->force_model == EVLB_FORCE_EV1, t);
+}
+
+size_t fields_lds_bytes(int halo) {
+  return sizeof(double) * ((size_t)(FTX + 2 * halo) * (FTY + 2 * halo) + 5 * (size_t)GX * GY);
+}
+
+}  // namespace
+
+struct Ctx {
+  evlb_params p;
+  int nx, ny;
+  long long N;
+  Layout L;
+  Dev dev;
+  char* ws;
+  const double *vel, *meq, *dpm, *avg_w, *pair_cx, *pair_cy;
+  const int *avg_ofs, *pair_ofs;
+  std::vector<double> hvel;
+};
+
+int validate(const evlb_params* p) {
+  if (!p || p->dim != 2) return EVLB_EINVAL;
+  if (p->n_sys != 1 || !p->nx) return EVLB_EINVAL;
+  if (p->nx[0] < 8 || p->ny < 8) return EVLB_EINVAL;
+  const long long N = (long long)p->nx[0] * p->ny;
+  if (N > (1ll << 30)) return EVLB_EINVAL;
+  if (p->q != Q) return EVLB_EUNSUPPORTED;
+  if (!(p->dx > 0) || !(p->dt > 0) || !std::isfinite(p->dx) || !std::isfinite(p->dt)) return EVLB_EINVAL;
+  if (!(p->sigma > 0) || !std::isfinite(p->sigma) || !(p->phi_sigma >= 0) || !std::isfinite(p->phi_sigma))
+    return EVLB_EINVAL;
+  if (p->force_model < 0 || p->force_model > 2) return EVLB_EINVAL;
+  if (p->force_model == EVLB_FORCE_EV2) return EVLB_EUNSUPPORTED;
+  if (p->gamma != 6.0) return EVLB_EUNSUPPORTED;  // the z-integrated kernel is tabulated for gamma = 6
+  if (p->term_mask & ~EVLB_TERM_ALL) return EVLB_EINVAL;
+  if (!(p->weno_eps > 0) || !std::isfinite(p->g_ext)) return EVLB_EINVAL;
+  if (p->exec_mode < 0 || p->exec_mode > 2) return EVLB_EINVAL;
+  if (p->exec_mode == EVLB_EXEC_PERSISTENT) return EVLB_EUNSUPPORTED;
+  if (p->tile_nodes != 0) return EVLB_EINVAL;
+  if (p->adjoint != 0 && p->adjoint != 1) return EVLB_EINVAL;
+  if (p->adjoint) return EVLB_EUNSUPPORTED;
+  if ((int)std::ceil(p->sigma / p->dx) + 2 > HMAX) return EVLB_EINVAL;
+  if (p->force_model == EVLB_FORCE_EV1) {
+    int mf;
+    if (!is_integer_multiple(p->r_cut, p->dx, &mf) || mf > HMAX) return EVLB_EINVAL;
+  }
+  // WENO-5 + TVD-RK3 along two axes: dt (|p_x| + |p_y|)_max / dx <= 1
+  std::vector<double> v, w;
+  evlb::gauss_hermite_nodes(Q, v, w);
+  if (p->dt * 2.0 * v.back() / p->dx > 1.0) return EVLB_ECFL;
+  return EVLB_OK;
+}
+
+size_t workspace_bytes(const evlb_params* p) {
+  if (validate(p) != EVLB_OK) return 0;
+  evlb::DiscTables t;
+  disc_tables(p, t);
+  return make_layout(p, t).total;
+}
+
+int init(const evlb_params* p, char* ws, size_t bytes, Ctx** out) {
+  *out = nullptr;
+  int rc = validate(p);
+  if (rc) return rc;
+  evlb::DiscTables t;
+  disc_tables(p, t);
+  const Layout L = make_layout(p, t);
+  if (!ws || bytes < L.total || ((uintptr_t)ws & 255)) return EVLB_EWORKSPACE;
+  Ctx* c = new (std::nothrow) Ctx();
+  if (!c) return EVLB_EINVAL;
+  c->p = *p;
+  c->nx = p->nx[0];
+  c->ny = p->ny;
+  c->N = (long long)c->nx * c->ny;
+  c->L = L;
+  c->ws = ws;
+  evlb::TableParams tp{Q, p->dx, p->sigma, p->phi_sigma, p->gamma, p->r_cut};
+  evlb::HostTables ht;
+  evlb::build_tables(tp, ht);
+  c->hvel = ht.vel;
+  const int PX = FTX + 2 * L.halo;
+  std::vector<double> hd;
+  hd.insert(hd.end(), ht.vel.begin(), ht.vel.end());
+  hd.insert(hd.end(), ht.meq.begin(), ht.meq.end());
+  hd.insert(hd.end(), ht.dpm.begin(), ht.dpm.end());
+  hd.insert(hd.end(), t.avg_w.begin(), t.avg_w.end());
+  const size_t o_cx = hd.size();
+  hd.insert(hd.end(), t.pair_cx.begin(), t.pair_cx.end());
+  if (t.pair_cx.empty()) hd.push_back(0.0);
+  const size_t o_cy = hd.size();
+  hd.insert(hd.end(), t.pair_cy.begin(), t.pair_cy.end());
+  if (t.pair_cy.empty()) hd.push_back(0.0);
+  std::vector<int> hi;
+  for (size_t i = 0; i < t.avg_w.size(); ++i) hi.push_back(t.avg_dj[i] * PX + t.avg_di[i]);
+  const size_t o_po = hi.size();
+  for (size_t i = 0; i < t.pair_cx.size(); ++i) hi.push_back(t.pair_dj[i] * PX + t.pair_di[i]);
+  if (t.pair_cx.empty()) hi.push_back(0);
+  double* tabd = (double*)(ws + L.tab_d);
+  int* tabi = (int*)(ws + L.tab_i);
+  if (hipMemcpy(tabd, hd.data(), hd.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(tabi, hi.data(), hi.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemset(ws + L.status, 0, 256) != hipSuccess) {
+    delete c;
+    return EVLB_EHIP;
+  }
+  c->vel = tabd;
+  c->meq = tabd + Q;
+  c->dpm = tabd + Q + Q * Q;
+  c->avg_w = tabd + Q + 2 * Q * Q;
+  c->pair_cx = tabd + o_cx;
+  c->pair_cy = tabd + o_cy;
+  c->avg_ofs = tabi;
+  c->pair_ofs = tabi + o_po;
+  Dev& d = c->dev;
+  d.nx = c->nx;
+  d.ny = c->ny;
+  d.ntot = c->N;
+  d.inv_dx = 1.0 / p->dx;
+  const double sg = p->sigma;
+  d.b = 2.0 * M_PI * sg * sg * sg / 3.0;
+  d.eta_c = M_PI * sg * sg * sg / 6.0;
+  d.mu0c = 5.0 / (16.0 * sg * sg * std::sqrt(M_PI));
+  d.weno_eps = p->weno_eps;
+  d.g_ext = p->g_ext;
+  d.force_model = p->force_model;
+  d.term_mask = p->term_mask;
+  d.navg = L.navg;
+  d.npair = p->force_model == EVLB_FORCE_EV1 ? L.npair : 0;
+  d.halo = L.halo;
+  d.status = (int*)(ws + L.status);
+  *out = c;
+  return EVLB_OK;
+}
+
+void destroy(Ctx* c) { delete c; }
+long long node_count(const Ctx* c) { return c->N; }
+const std::vector<double>& velocities(const Ctx* c) { return c->hvel; }
+int* status_word(const Ctx* c) { return c->dev.status; }
+
+namespace {
+
+int launched() { return hipGetLastError() == hipSuccess ? EVLB_OK : EVLB_EHIP; }
+
+int launch_moments(Ctx* c, const double* f, double* out6, hipStream_t st) {
+  const unsigned nb = (unsigned)((c->N + 255) / 256);
+  hipLaunchKernelGGL(moments_kernel, dim3(nb), dim3(256), 0, st, c->dev, f, out6, c->vel);
+  return launched();
+}
+
+int launch_fields(Ctx* c, hipStream_t st) {
+  const dim3 grid((c->nx + FTX - 1) / FTX, (c->ny + FTY - 1) / FTY);
+  hipLaunchKernelGGL(fields_kernel, grid, dim3(FNT), fields_lds_bytes(c->L.halo), st, c->dev,
+                     (const double*)(c->ws + c->L.mom), (double*)(c->ws + c->L.fld), c->avg_ofs, c->avg_w,
+                     c->pair_ofs, c->pair_cx, c->pair_cy);
+  return launched();
+}
+
+int launch_adv(Ctx* c, const AdvArgs& A, hipStream_t st) {
+  const long long nb = (long long)((c->nx + ATX - 1) / ATX) * ((c->ny + ATY - 1) / ATY) * 2 * V;
+  hipLaunchKernelGGL(adv_kernel, dim3((unsigned)nb), dim3(ANT), 0, st, c->dev, A, c->vel);
+  return launched();
+}
+
+int launch_vel(Ctx* c, const VelArgs& A, hipStream_t st) {
+  const unsigned nb = (unsigned)(((c->nx + 63) / 64) * c->ny);
+  hipLaunchKernelGGL(vel_kernel, dim3(nb), dim3(256), 0, st, c->dev, A, c->vel, c->meq, c->dpm);
+  return launched();
+}
+
+// one evaluation: fields of the moments in the workspace, then
+// W = a f0 + b fs + c Adv(fs) and out = W + c R(fs)
+int stage(Ctx* c, const double* fs, const double* f0, double* W, double a, double b, double cc, int first,
+          int want_mom, hipStream_t st) {
+  int rc = launch_fields(c, st);
+  if (rc) return rc;
+  AdvArgs A{fs, f0, W, a, b, cc, first};
+  rc = launch_adv(c, A, st);
+  if (rc) return rc;
+  VelArgs B{fs, W, (const double*)(c->ws + c->L.fld), (double*)(c->ws + c->L.mom), cc, want_mom};
+  return launch_vel(c, B, st);
+}
+
+}  // namespace
+
+int set_equilibrium(Ctx* c, const double* n, const double* u, const double* T, double* f, hipStream_t st) {
+  const unsigned nb = (unsigned)((c->N + 255) / 256);
+  hipLaunchKernelGGL(equilibrium_kernel, dim3(nb), dim3(256), 0, st, c->dev, n, u, T, f, c->meq);
+  return launched();
+}
+
+int step(Ctx* c, double* f, int nsteps, hipStream_t st) {
+  static const double RKA[3] = {0.0, 0.75, 1.0 / 3.0};
+  static const double RKB[3] = {1.0, 0.25, 2.0 / 3.0};
+  double* f1 = (double*)(c->ws + c->L.f1);
+  double* f2 = (double*)(c->ws + c->L.f2);
+  int rc = launch_moments(c, f, (double*)(c->ws + c->L.mom), st);
+  if (rc) return rc;
+  const double dt = c->p.dt;
+  for (int n = 0; n < nsteps; ++n) {
+    for (int s = 0; s < 3; ++s) {
+      const double* fs = s == 0 ? f : (s == 1 ? f1 : f2);
+      double* W = s == 0 ? f1 : (s == 1 ? f2 : f);  // stage 3 overwrites f^n in place, element by element
+      rc = stage(c, fs, f, W, RKA[s], RKB[s], RKB[s] * dt, s == 0, 1, st);
+      if (rc) return rc;
+    }
+  }
+  return EVLB_OK;
+}
+
+int rhs(Ctx* c, const double* f, double* L, hipStream_t st) {
+  int rc = launch_moments(c, f, (double*)(c->ws + c->L.mom), st);
+  if (rc) return rc;
+  return stage(c, f, f, L, 0.0, 0.0, 1.0, 1, 0, st);
+}
+
+int moments(Ctx* c, const double* f, double* n, double* u, double* T, double* q, hipStream_t st) {
+  double* m = (double*)(c->ws + c->L.mom);
+  int rc = launch_moments(c, f, m, st);
+  if (rc) return rc;
+  const size_t nb = sizeof(double) * (size_t)c->N;
+  if (hipMemcpyAsync(n, m, nb, hipMemcpyDeviceToDevice, st) != hipSuccess ||
+      hipMemcpyAsync(u, m + c->N, 2 * nb, hipMemcpyDeviceToDevice, st) != hipSuccess ||
+      hipMemcpyAsync(T, m + 3 * c->N, nb, hipMemcpyDeviceToDevice, st) != hipSuccess)
+    return EVLB_EHIP;
+  if (q && hipMemcpyAsync(q, m + 4 * c->N, 2 * nb, hipMemcpyDeviceToDevice, st) != hipSuccess) return EVLB_EHIP;
+  return EVLB_OK;
+}
+
+}  // namespace evlb2d

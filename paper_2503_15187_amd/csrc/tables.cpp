@@ -153,4 +153,60 @@ void build_tables(const TableParams& tp, HostTables& t) {
   }
 }
 
+// 2D disc stencils.
+//
+// Averaged density: the ball average of Sec. II A integrated over z is a disc
+// average with weight 2 sqrt(sigma^2 - s^2) (the chord of the ball); the
+// weights of the cells with s < sigma are normalised to sum 1.
+//
+// Force: a line of density along z at in-plane distance s acts through the
+// tail of eq:sutherland (gamma = 6) outside the hard core; with z = s tan t,
+//   K(s) = 12 phi sigma^6 s^-7 I(psi),  I(psi) = int_0^psi sin^6 t dt
+//        = 5 psi/16 - 15 sin(2 psi)/64 + 3 sin(4 psi)/64 - sin(6 psi)/192,
+// psi = asin(s/sigma) inside the core and pi/2 outside.  The force on a node
+// is sum over cells of K(s) (s_vec / s) n dx^2, taken as antisymmetric pairs
+// +-s: F = sum_pairs c (n(+s) - n(-s)).
+void build_disc_tables(double dx, double sigma, double phi, double r_cut, bool force, DiscTables& t) {
+  const ld pi = 3.141592653589793238462643383279502884L;
+  const ld h = dx, sg = sigma;
+  t = DiscTables();
+  const int ma = (int)std::ceil(sigma / dx);
+  ld wsum = 0.0L;
+  std::vector<ld> wl;
+  for (int j = -ma; j <= ma; ++j) {
+    for (int i = -ma; i <= ma; ++i) {
+      const ld s2 = (ld)(i * i + j * j) * h * h;
+      if (!(s2 < sg * sg)) continue;
+      const ld w = 2.0L * std::sqrt(sg * sg - s2);
+      t.avg_di.push_back(i);
+      t.avg_dj.push_back(j);
+      wl.push_back(w);
+      wsum += w;
+      if (std::abs(i) > t.avg_reach) t.avg_reach = std::abs(i);
+      if (std::abs(j) > t.avg_reach) t.avg_reach = std::abs(j);
+    }
+  }
+  for (ld w : wl) t.avg_w.push_back((double)(w / wsum));
+  if (!force) return;
+  const int mf = (int)std::lround(r_cut / dx);
+  for (int j = -mf; j <= mf; ++j) {
+    for (int i = -mf; i <= mf; ++i) {
+      if (i * i + j * j > mf * mf || i * i + j * j == 0) continue;
+      if (!(i > 0 || (i == 0 && j > 0))) continue;
+      const ld s = h * std::sqrt((ld)(i * i + j * j));
+      const ld psi = s < sg ? std::asin(s / sg) : 0.5L * pi;
+      const ld I = 5.0L * psi / 16.0L - 15.0L * std::sin(2.0L * psi) / 64.0L +
+                   3.0L * std::sin(4.0L * psi) / 64.0L - std::sin(6.0L * psi) / 192.0L;
+      const ld sg3 = sg * sg * sg;
+      const ld K = 12.0L * (ld)phi * sg3 * sg3 * I / std::pow(s, 7);
+      t.pair_di.push_back(i);
+      t.pair_dj.push_back(j);
+      t.pair_cx.push_back((double)(K * (ld)i * h * h * h));
+      t.pair_cy.push_back((double)(K * (ld)j * h * h * h));
+      if (std::abs(i) > t.pair_reach) t.pair_reach = std::abs(i);
+      if (std::abs(j) > t.pair_reach) t.pair_reach = std::abs(j);
+    }
+  }
+}
+
 }  // namespace evlb

@@ -14,7 +14,7 @@ import torch
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libevlb.so")
 
-EVLB_ABI_VERSION = 1
+EVLB_ABI_VERSION = 2
 EVLB_OK, EVLB_EINVAL, EVLB_ECFL, EVLB_EWORKSPACE, EVLB_EHIP, EVLB_ENONFINITE, EVLB_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 EVLB_FORCE_EV1, EVLB_FORCE_EV2, EVLB_FORCE_NONE = 0, 1, 2
 EVLB_TERM_ADV, EVLB_TERM_FORCE, EVLB_TERM_J0, EVLB_TERM_J1, EVLB_TERM_ALL = 1, 2, 4, 8, 15
@@ -41,6 +41,7 @@ class evlb_params(ctypes.Structure):
         ("exec_mode", ctypes.c_int32),
         ("tile_nodes", ctypes.c_int32),
         ("adjoint", ctypes.c_int32),
+        ("ny", ctypes.c_int32),
     ]
 
 
@@ -101,14 +102,16 @@ def _check(code, what):
 
 def make_params(q, dx, dt, nx, sigma=1.0, phi_sigma=1.0, gamma=6.0, r_cut=5.0,
                 force_model=EVLB_FORCE_EV1, term_mask=EVLB_TERM_ALL, weno_eps=1e-6,
-                g_ext=0.0, exec_mode=EVLB_EXEC_AUTO, tile_nodes=0, adjoint=0):
-    """evlb_params for one or several periodic 1D systems (nx: int or list).
-    The returned structure keeps its nx array alive."""
+                g_ext=0.0, exec_mode=EVLB_EXEC_AUTO, tile_nodes=0, adjoint=0, ny=0):
+    """evlb_params for one or several periodic 1D systems (nx: int or list),
+    or, with ny > 0, one periodic nx x ny 2D system (dim 2).  The returned
+    structure keeps its nx array alive."""
     nxs = [int(nx)] if isinstance(nx, (int,)) else [int(v) for v in nx]
     arr = (ctypes.c_int32 * len(nxs))(*nxs)
-    p = evlb_params(EVLB_ABI_VERSION, 1, len(nxs), arr, int(q), float(dx), float(dt), float(sigma),
+    dim = 2 if ny else 1
+    p = evlb_params(EVLB_ABI_VERSION, dim, len(nxs), arr, int(q), float(dx), float(dt), float(sigma),
                     float(phi_sigma), float(gamma), float(r_cut), int(force_model), int(term_mask),
-                    float(weno_eps), float(g_ext), int(exec_mode), int(tile_nodes), int(adjoint))
+                    float(weno_eps), float(g_ext), int(exec_mode), int(tile_nodes), int(adjoint), int(ny))
     p._nx_keepalive = arr
     return p
 
@@ -207,11 +210,15 @@ def evlb_destroy(ctx):
 
 
 class Solver:
-    """A context plus its workspace on the current device."""
+    """A context plus its workspace on the current device.  With ny > 0 the
+    context is the 2D path: states are (2, q, q, ny, nx) and vector node
+    fields (u, q) carry an x and a y component."""
 
     def __init__(self, q, dx, dt, nx, device=None, stream=None, **kw):
         self.params = make_params(q, dx, dt, nx, **kw)
         self.q = int(q)
+        self.dim = int(self.params.dim)
+        self.shape2d = (int(self.params.ny), int(nx)) if self.dim == 2 else None
         nbytes = evlb_workspace_bytes(self.params)
         if nbytes == 0:
             _check(evlb_validate(self.params) or EVLB_EINVAL, "evlb_workspace_bytes")
@@ -231,6 +238,8 @@ class Solver:
         self.ctx = None
 
     def new_state(self):
+        if self.dim == 2:
+            return torch.empty((2, self.q, self.q) + self.shape2d, dtype=torch.float64, device=self.device)
         return torch.empty((2, self.q, self.n_tot), dtype=torch.float64, device=self.device)
 
     def equilibrium(self, n, u, T, stream=None):
@@ -248,6 +257,12 @@ class Solver:
         return L
 
     def moments(self, f, stream=None):
+        """(4, n_tot) = n, u, T, q in 1D; (6, n_tot) = n, u_x, u_y, T, q_x,
+        q_y in 2D."""
+        if self.dim == 2:
+            out = torch.empty((6, self.n_tot), dtype=torch.float64, device=self.device)
+            evlb_moments(self.ctx, f, out[0], out[1:3], out[3], out[4:6], stream)
+            return out
         out = torch.empty((4, self.n_tot), dtype=torch.float64, device=self.device)
         evlb_moments(self.ctx, f, out[0], out[1], out[2], out[3], stream)
         return out

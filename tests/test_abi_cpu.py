@@ -93,3 +93,60 @@ def test_null_context_rejected():
 def test_strerror():
     for code in (0, -1, -2, -3, -4, -5, -6, -77):
         assert isinstance(P.strerror(code), str) and P.strerror(code)
+
+
+# ---------------------------------------------------------------------------
+# dim = 2
+# ---------------------------------------------------------------------------
+DT2D = 0.2 * 0.25 / 6.630878198393129
+
+
+def _p2(**kw):
+    base = dict(q=16, dx=0.25, dt=DT2D, nx=1024, ny=1024)
+    base.update(kw)
+    return P.make_params(**base)
+
+
+def test_validate_accepts_2d_workload():
+    p = _p2()
+    assert p.dim == 2
+    assert P.evlb_validate(p) == E.EVLB_OK
+    assert P.evlb_validate(_p2(nx=40, ny=24)) == E.EVLB_OK
+    assert P.evlb_validate(_p2(force_model=E.EVLB_FORCE_NONE)) == E.EVLB_OK
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(q=8), E.EVLB_EUNSUPPORTED),
+    (dict(gamma=8.0), E.EVLB_EUNSUPPORTED),
+    (dict(force_model=E.EVLB_FORCE_EV2), E.EVLB_EUNSUPPORTED),
+    (dict(adjoint=1), E.EVLB_EUNSUPPORTED),
+    (dict(exec_mode=E.EVLB_EXEC_PERSISTENT), E.EVLB_EUNSUPPORTED),
+    (dict(tile_nodes=64), E.EVLB_EINVAL),
+    (dict(ny=4), E.EVLB_EINVAL),
+    (dict(nx=[64, 64]), E.EVLB_EINVAL),
+    (dict(r_cut=5.1), E.EVLB_EINVAL),       # r_cut/dx not an integer
+    (dict(r_cut=7.0), E.EVLB_EINVAL),       # force disc above the built maximum
+    (dict(dt=0.2), E.EVLB_ECFL),
+    (dict(dt=0.6 * 0.25 / 6.630878198393129), E.EVLB_ECFL),  # 1D limit met, 2D sum exceeded
+])
+def test_validate_rejects_2d(kw, code):
+    p = _p2(**kw)
+    assert P.evlb_validate(p) == code
+    assert P.evlb_workspace_bytes(p) == 0
+
+
+def test_workspace_2d_scales_with_nodes():
+    a = P.evlb_workspace_bytes(_p2(nx=256, ny=256))
+    b = P.evlb_workspace_bytes(_p2(nx=256, ny=512))
+    # two stage buffers [2][256][n], moments [6][n] and node fields [18][n]
+    per_node = 2 * 2 * 256 * 8 + 6 * 8 + 18 * 8
+    assert abs((b - a) - 256 * 256 * per_node) < 4096
+
+
+def test_init_2d_rejects_missing_workspace_before_device_work():
+    p = _p2(nx=64, ny=64)
+    out = ctypes.c_void_p()
+    L = P.lib()
+    assert L.evlb_init(ctypes.byref(p), None, 0, None, ctypes.byref(out)) == E.EVLB_EWORKSPACE
+    assert L.evlb_init(ctypes.byref(p), ctypes.c_void_p(256), 16, None, ctypes.byref(out)) == E.EVLB_EWORKSPACE
+    assert out.value is None
