@@ -387,12 +387,14 @@ struct VelArgs {
 };
 
 // Lane (nd, g) = (lane & 15, lane >> 4) owns node x = x_w + nd and the velocity
-// rows k = 4 g + j, j < 4, for every l: M[j][l] = f[k][l] (64 values).
-// (Dp x I) M on the MFMA: D = sum_b A_b B_b over b < 4 with A_b[i][c] =
-// Dp[i][4c + b] (lane holds Dp[nd][4g + b]) and B_b[c][node] = M_node[4c + b][l]
-// (lane holds M[b][l]); the 16 x 16 result D[k][node] comes back as
-// D[4g + j][nd] in element j of the lane's accumulator, the same rows the lane
-// owns.  (I x Dp) M contracts over l, which the lane holds whole: VALU.
+// rows k = g + 4 j, j < 4, for every l: M[j][l] = f[k][l] (64 values).
+// (Dp x I) M on the MFMA (v_mfma_f64_16x16x4: A operand element [i][c] from
+// lane i + 16 c, B operand element [c][col] from lane col + 16 c, result
+// element [4 j + c][col] in register j of lane col + 16 c): D = sum_b A_b B_b
+// over b < 4 with A_b[i][c] = Dp[i][c + 4b] (lane holds Dp[nd][g + 4b]) and
+// B_b[c][node] = M_node[c + 4b][l] (lane holds M[b][l]); D[k][node] comes back
+// as D[g + 4j][nd] in register j, the rows the lane owns.  (I x Dp) M
+// contracts over l, which the lane holds whole: VALU.
 __global__ __launch_bounds__(256) void vel_kernel(Dev D, VelArgs A, const double* __restrict__ vel,
                                                   const double* __restrict__ meq,
                                                   const double* __restrict__ dpm) {
@@ -431,14 +433,14 @@ __global__ __launch_bounds__(256) void vel_kernel(Dev D, VelArgs A, const double
       double s = 0.0;
 #pragma unroll
       for (int m = 0; m < Q; ++m) s += meq[k * Q + m] * a[m];
-      if ((k >> 2) == g) ex[k & 3] = s;
+      if ((k & 3) == g) ex[k >> 2] = s;
     }
   }
   double pkv[4], aop[4];
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
-    pkv[j] = vel[4 * g + j];
-    aop[j] = dpm[nd * Q + 4 * g + j];
+    pkv[j] = vel[g + 4 * j];
+    aop[j] = dpm[nd * Q + g + 4 * j];
   }
   const bool frc = (D.term_mask & EVLB_TERM_FORCE) != 0;
   const bool j0 = (D.term_mask & EVLB_TERM_J0) != 0;
@@ -461,7 +463,7 @@ __global__ __launch_bounds__(256) void vel_kernel(Dev D, VelArgs A, const double
 #pragma unroll
     for (int j = 0; j < 4; ++j)
 #pragma unroll
-      for (int l = 0; l < Q; ++l) M[j][l] = src[(long long)((4 * g + j) * Q + l) * N];
+      for (int l = 0; l < Q; ++l) M[j][l] = src[(long long)((g + 4 * j) * Q + l) * N];
     // F: F^S = E [1 + s(xi.q)(th - 4)], J1F; G: T/2 E, th - 2 (reduction over p_z)
     const double tf = d == 0 ? 1.0 : 0.5 * T;
     const double th0 = d == 0 ? 4.0 : 2.0;
@@ -506,7 +508,7 @@ __global__ __launch_bounds__(256) void vel_kernel(Dev D, VelArgs A, const double
                               xy * xy * fl[F_UYY]) * it_d;
           R += fl[F_PRE] * tf * E * (xA + 0.3 * (th - th0) * xB + 0.4 * (xxu + 0.5 * (th - th0) * div));
         }
-        const long long o = (long long)((4 * g + j) * Q + l) * N;
+        const long long o = (long long)((g + 4 * j) * Q + l) * N;
         const double out = wio[o] + A.c * R;
         if (valid) wio[o] = out;
         if (d == 0) {
