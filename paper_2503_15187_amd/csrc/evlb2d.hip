@@ -15,8 +15,9 @@
 //                  (eq:carnstar), force (antisymmetric cell pairs), transport
 //                  (eq:viscosity, eq:tau, eq:prandtl), 4th-order central
 //                  gradients of X = n^2 chi T, T and u along x and y.
-//   adv_kernel     one velocity plane x a 64 x 16 tile per workgroup: the tile
-//                  and a 3-node halo in LDS, every WENO-5 face computed once,
+//   adv_kernel     one wavefront per strip of 58 columns x 64 rows of one
+//                  velocity plane, marching down the rows with a register
+//                  window; every WENO-5 face computed once,
 //                  W = a f^n + b f^(s-1) + c Adv(f^(s-1)).
 //   vel_kernel     16 nodes per wavefront, lanes = (node, group g of four p_x
 //                  rows): d/dp_x as (Dp x I) on the f64 MFMA (the node's 16 x 16
@@ -292,11 +293,17 @@ __global__ __launch_bounds__(FNT) void fields_kernel(Dev D, const double* __rest
 }
 
 // ---------------------------------------------------------------------------
-// advection: one velocity plane x one 64 x 16 tile
+// advection: one wavefront per strip of 58 columns x AR rows of one plane
 // ---------------------------------------------------------------------------
-constexpr int ATX = 64, ATY = 16, ANT = 256;
-constexpr int APX = ATX + 6, APY = ATY + 6;
-constexpr int NXF = ATY * (ATX + 1), NYF = (ATY + 1) * ATX;
+// Lane t holds column x0 - 3 + t (t < 64) and marches down the rows with a
+// register window of the six rows y - 2 .. y + 3.  The face between rows y and
+// y + 1 is computed once and reused as the upper face of the next row; the
+// face between columns x - 1 and x is computed by lane t from the row values
+// of lanes t - 3 .. t + 2 (shuffles) and the lane's right face comes from
+// lane t + 1.  Lanes 3 .. 60 produce the 58 outputs.  No LDS, no barrier.
+constexpr int AW = 58;   // output columns per wavefront
+constexpr int AR = 64;   // output rows per wavefront
+constexpr int ANT = 256; // four strips per workgroup
 
 struct AdvArgs {
   const double* fs;  // f^(s-1)
@@ -306,76 +313,103 @@ struct AdvArgs {
   int first;         // f0 == fs
 };
 
+__device__ __forceinline__ double face(const double* w, bool pos, double eps) {
+  return pos ? weno5(w[0], w[1], w[2], w[3], w[4], eps) : weno5(w[5], w[4], w[3], w[2], w[1], eps);
+}
+
 __global__ __launch_bounds__(ANT) void adv_kernel(Dev D, AdvArgs A, const double* __restrict__ vel) {
-  __shared__ double sf[APY * APX];  // node (x0 - 3 + c, y0 - 3 + r)
-  __shared__ double xf[NXF];        // face x0 + fx - 1/2 of row r: [r][fx]
-  __shared__ double yf[NYF];        // face y0 + fy - 1/2 of column c: [fy][c]
-  const int ntx = (D.nx + ATX - 1) / ATX, nty = (D.ny + ATY - 1) / ATY;
+  const int nsx = (D.nx + AW - 1) / AW, nsy = (D.ny + AR - 1) / AR;
   // consecutive workgroups go to different XCDs; hand each XCD a contiguous
-  // range of tiles so that the y-halo rows of a tile row meet in its L2
+  // range of strips so that neighbouring strips share its L2
   unsigned b = blockIdx.x;
   const unsigned nb = gridDim.x;
   if ((nb & 7u) == 0) b = (b & 7u) * (nb >> 3) + (b >> 3);
-  const int tx = (int)(b % (unsigned)ntx);
-  b /= (unsigned)ntx;
-  const int ty = (int)(b % (unsigned)nty);
-  const int plane = (int)(b / (unsigned)nty);
+  const unsigned strip = b * 4u + (threadIdx.x >> 6);
+  const unsigned per_plane = (unsigned)nsx * (unsigned)nsy;
+  const int plane = (int)(strip / per_plane);
+  if (plane >= 2 * V) return;  // whole wavefront past the last strip
+  const unsigned sp = strip - (unsigned)plane * per_plane;
+  const int sy = (int)(sp / (unsigned)nsx), sx = (int)(sp - (unsigned)sy * (unsigned)nsx);
   const int v = plane % V, k = v / Q, l = v - k * Q;
   const double px = vel[k], py = vel[l];
+  const bool posx = px > 0.0, posy = py > 0.0;
   const long long base = (long long)plane * D.ntot;
   const double* fs = A.fs + base;
-  const int x0 = tx * ATX, y0 = ty * ATY;
-  const int tid = threadIdx.x;
-  const bool adv = (D.term_mask & EVLB_TERM_ADV) != 0;
-  if (adv) {
-    for (int i = tid; i < APX * APY; i += ANT) {
-      const int r = i / APX, c = i - r * APX;
-      sf[i] = fs[(long long)wrap(y0 - 3 + r, D.ny) * D.nx + wrap(x0 - 3 + c, D.nx)];
-    }
-    __syncthreads();
-    const bool posx = px > 0.0, posy = py > 0.0;
-    for (int t = tid; t < NXF + NYF; t += ANT) {
-      if (t < NXF) {
-        // face between nodes x0 + fx - 1 and x0 + fx; upwind by the sign of p_x
-        const int r = t / (ATX + 1), fx = t - r * (ATX + 1);
-        const double* row = sf + (r + 3) * APX;
-        const int c0 = posx ? fx : fx + 5;
-        const int st = posx ? 1 : -1;
-        xf[t] = weno5(row[c0], row[c0 + st], row[c0 + 2 * st], row[c0 + 3 * st], row[c0 + 4 * st], D.weno_eps);
-      } else {
-        const int u = t - NXF;
-        const int fy = u / ATX, c = u - fy * ATX;
-        const double* col = sf + c + 3;
-        const int r0 = posy ? fy : fy + 5;
-        const int st = posy ? APX : -APX;
-        const int o = r0 * APX;
-        yf[u] = weno5(col[o], col[o + st], col[o + 2 * st], col[o + 3 * st], col[o + 4 * st], D.weno_eps);
-      }
-    }
-    __syncthreads();
+  const int t = threadIdx.x & 63;
+  const int x0 = sx * AW, y0 = sy * AR;
+  const int xc = wrap(x0 - 3 + t, D.nx);
+  const bool outcol = t >= 3 && t < 3 + AW && x0 + t - 3 < D.nx;
+  const double eps = D.weno_eps;
+  // window rows y0 - 3 .. y0 + 2
+  double w[6];
+  int yr = wrap(y0 - 3, D.ny);
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    w[i] = fs[(long long)yr * D.nx + xc];
+    if (++yr == D.ny) yr = 0;
   }
-  for (int o = tid; o < ATX * ATY; o += ANT) {
-    const int r = o / ATX, c = o - r * ATX;
-    const int x = x0 + c, y = y0 + r;
-    if (x >= D.nx || y >= D.ny) continue;
-    const long long node = (long long)y * D.nx + x;
-    double fv, av = 0.0;
-    if (adv) {
-      fv = sf[(r + 3) * APX + c + 3];
-      av = -(px * (xf[r * (ATX + 1) + c + 1] - xf[r * (ATX + 1) + c]) +
-             py * (yf[(r + 1) * ATX + c] - yf[r * ATX + c])) * D.inv_dx;
+  double fyl = face(w, posy, eps);  // face between rows y0 - 1 and y0
+  // yr is now row y0 + 3
+  for (int r = 0; r < AR; ++r) {
+    const int y = y0 + r;
+#pragma unroll
+    for (int i = 0; i < 5; ++i) w[i] = w[i + 1];
+    w[5] = fs[(long long)yr * D.nx + xc];  // row y + 3
+    if (++yr == D.ny) yr = 0;
+    const double fyr = face(w, posy, eps);  // face between rows y and y + 1
+    // row values of the neighbouring columns
+    const double c0 = w[2];
+    const double m1 = __shfl_up(c0, 1), m2 = __shfl_up(c0, 2), p1 = __shfl_down(c0, 1);
+    double fxl;
+    if (posx) {
+      const double m3 = __shfl_up(c0, 3);
+      fxl = weno5(m3, m2, m1, c0, p1, eps);   // face between columns x - 1 and x
     } else {
-      fv = fs[node];
+      const double p2 = __shfl_down(c0, 2);
+      fxl = weno5(p2, p1, c0, m1, m2, eps);
     }
-    const double f0v = A.first ? fv : A.f0[base + node];
-    A.W[base + node] = A.a * f0v + A.b * fv + A.c * av;
+    const double fxr = __shfl_down(fxl, 1);
+    if (outcol && y < D.ny) {
+      const long long node = (long long)y * D.nx + xc;
+      const double adv = -(px * (fxr - fxl) + py * (fyr - fyl)) * D.inv_dx;
+      const double f0v = A.first ? c0 : A.f0[base + node];
+      A.W[base + node] = A.a * f0v + A.b * c0 + A.c * adv;
+    }
+    fyl = fyr;
   }
+}
+
+// W = a f^n + b f^(s-1) without advection (term tests)
+__global__ __launch_bounds__(256) void combine_kernel(Dev D, AdvArgs A) {
+  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (i >= 2 * V * D.ntot) return;
+  const double fv = A.fs[i];
+  const double f0v = A.first ? fv : A.f0[i];
+  A.W[i] = A.a * f0v + A.b * fv;
 }
 
 // ---------------------------------------------------------------------------
 // velocity space: 16 nodes per wavefront
 // ---------------------------------------------------------------------------
 typedef double dbl4 __attribute__((ext_vector_type(4)));
+typedef unsigned u32x2 __attribute__((__vector_size__(2 * sizeof(unsigned))));
+
+// Raw buffer access: a uniform base (SGPRs) plus a 32-bit per-lane byte
+// offset; an offset at or above num_records is out of range, so the store is
+// dropped (lanes past the row end) without a branch.
+constexpr int BUF_DWORD3 = 0x00020000;
+constexpr unsigned BUF_RANGE = 0x7fffffffu;
+constexpr unsigned BUF_OFF = 0xfffffff0u;  // out of range
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf(const double* base) {
+  return __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, (int)BUF_RANGE, BUF_DWORD3);
+}
+__device__ __forceinline__ double bload(const double* base, unsigned vo) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(buf(base), vo, 0, 0));
+}
+__device__ __forceinline__ void bstore(double v, double* base, unsigned vo) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), buf(base), vo, 0, 0);
+}
 
 struct VelArgs {
   const double* fs;   // f^(s-1)
@@ -395,9 +429,21 @@ struct VelArgs {
 // B_b[c][node] = M_node[c + 4b][l] (lane holds M[b][l]); D[k][node] comes back
 // as D[g + 4j][nd] in register j, the rows the lane owns.  (I x Dp) M
 // contracts over l, which the lane holds whole: VALU.
+//
+// Collision terms.  With xi = (xx, xy), th = |xi|^2 / T and the reduced
+// forms of the Shakhov and J1 terms (F: factor 1, th - 4; G: factor T/2,
+// th - 2), nu f^S + J1 = tf E P(xx, xy) with
+//   P = nu + pre (xx A_x + xy A_y) + (th - th0)(xx S_x + xy S_y + C)
+//       + 0.4 pre / T (xx^2 U_xx + xx xy (U_xy + U_yx) + xy^2 U_yy),
+//   S_x = nu s q_x + 0.3 pre B_x,  S_y = nu s q_y + 0.3 pre B_y,
+//   C = 0.2 pre div u,  pre = -b n chi.
+// For a fixed row (xx) P is a cubic in xy: alpha + xy (beta + xy (gamma +
+// delta xy)), set up once per row and pass.
+template <bool FRC>
 __global__ __launch_bounds__(256) void vel_kernel(Dev D, VelArgs A, const double* __restrict__ vel,
                                                   const double* __restrict__ meq,
                                                   const double* __restrict__ dpm) {
+  __shared__ double s_ey[4][16][Q];  // per wave: e_l(u_y) of its 16 nodes
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int nd = lane & 15, g = lane >> 4;
   const int nseg = (D.nx + 63) >> 6;
@@ -407,25 +453,22 @@ __global__ __launch_bounds__(256) void vel_kernel(Dev D, VelArgs A, const double
   const long long N = D.ntot;
   // lanes past the row end work on the last node and store nothing
   const long long node = (long long)y * D.nx + (valid ? x : D.nx - 1);
+  const bool j0 = (D.term_mask & EVLB_TERM_J0) != 0;
+  const bool j1 = (D.term_mask & EVLB_TERM_J1) != 0;
 
-  double fl[NF];
-#pragma unroll
-  for (int i = 0; i < NF; ++i) fl[i] = A.fld[i * N + node];
-  const double n = fl[F_N], ux = fl[F_UX], uy = fl[F_UY], T = fl[F_T];
-  const double invT = 1.0 / T;
-  const double div = fl[F_UXX] + fl[F_UYY];
-
-  // unit-density Hermite equilibria e_k(u_x) (own rows) and e_l(u_y) (all)
-  double ex[4] = {0.0, 0.0, 0.0, 0.0}, ey[Q];
+  // unit-density Hermite equilibria: e_k(u_x) of the own rows in registers,
+  // e_l(u_y) shared by the four lanes of a node through LDS
+  double ex[4] = {0.0, 0.0, 0.0, 0.0};
   {
+    const double ux = A.fld[F_UX * N + node], uy = A.fld[F_UY * N + node], T = A.fld[F_T * N + node];
     double a[Q];
     hermite_coeffs(uy, T, a);
 #pragma unroll
-    for (int l = 0; l < Q; ++l) {
+    for (int i = 0; i < 4; ++i) {
       double s = 0.0;
 #pragma unroll
-      for (int m = 0; m < Q; ++m) s += meq[l * Q + m] * a[m];
-      ey[l] = s;
+      for (int m = 0; m < Q; ++m) s += meq[(g + 4 * i) * Q + m] * a[m];
+      s_ey[wave][nd][g + 4 * i] = s;
     }
     hermite_coeffs(ux, T, a);
 #pragma unroll
@@ -442,93 +485,135 @@ __global__ __launch_bounds__(256) void vel_kernel(Dev D, VelArgs A, const double
     pkv[j] = vel[g + 4 * j];
     aop[j] = dpm[nd * Q + g + 4 * j];
   }
-  const bool frc = (D.term_mask & EVLB_TERM_FORCE) != 0;
-  const bool j0 = (D.term_mask & EVLB_TERM_J0) != 0;
-  const bool j1 = (D.term_mask & EVLB_TERM_J1) != 0;
+  __syncthreads();
+  const double* eyv = &s_ey[wave][nd][0];
 
+  // per-lane byte offset of (row g, node) from a plane base; < 2^31 by the
+  // node-count limit of the 2D path
+  const unsigned vo = (unsigned)(((long long)g * Q * N + node) * 8);
+  const unsigned vs = valid ? vo : BUF_OFF;
   Raw m{0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
 #pragma unroll 1
   for (int d = 0; d < 2; ++d) {
-    // Opaque copies: everything the F and G passes share is recomputed in
-    // each pass instead of being hoisted out of the loop, which would hold
-    // 64 equilibria, 256 Dp entries, ... live across both passes.
-    double n_d = n, ux_d = ux, uy_d = uy, it_d = invT;
-    const double* dp = dpm;
-    const double* vl = vel;
-    asm volatile("" : "+v"(n_d), "+v"(ux_d), "+v"(uy_d), "+v"(it_d));
-    asm volatile("" : "+s"(dp), "+s"(vl));
-    const double* src = A.fs + (long long)d * V * N + node;
-    double* wio = A.W + (long long)d * V * N + node;
+    // Opaque copies: what the F and G passes share (Dp rows, plane bases,
+    // node fields) is recomputed in each pass instead of being hoisted out of
+    // the loop and held live across both.
+    long long Nd = N;
+    int z = 0;  // an opaque zero keeps the pointers' address space and uniformity
+    asm volatile("" : "+s"(Nd), "+s"(z));
+    const double* dp = dpm + z;
+    const double* vl = vel + z;
+    const double* fd = A.fld + z;
+    const double* fsd = A.fs + (long long)d * V * Nd;
+    double* wd = A.W + (long long)d * V * Nd;
+    // plane of own row j (k = g + 4 j) and column l, relative to row g
+#define PLANE(base, j, l) ((base) + (long long)(4 * (j) * Q + (l)) * Nd)
     double M[4][Q];
 #pragma unroll
     for (int j = 0; j < 4; ++j)
 #pragma unroll
-      for (int l = 0; l < Q; ++l) M[j][l] = src[(long long)((g + 4 * j) * Q + l) * N];
-    // F: F^S = E [1 + s(xi.q)(th - 4)], J1F; G: T/2 E, th - 2 (reduction over p_z)
-    const double tf = d == 0 ? 1.0 : 0.5 * T;
-    const double th0 = d == 0 ? 4.0 : 2.0;
+      for (int l = 0; l < Q; ++l) M[j][l] = bload(PLANE(fsd, j, l), vo);
+    // W of column l is loaded PF columns ahead of its use
+    constexpr int PF = 1;
+    double wb[PF][4];
+#pragma unroll
+    for (int p = 0; p < PF; ++p)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) wb[p][j] = bload(PLANE(wd, j, p), vo);
+
+    // row polynomials of the collision terms
+    double al[4], be[4], ga[4], ne[4], de, nu, Fx, Fy, uy;
+    {
+      const double n = fd[F_N * Nd + node], ux = fd[F_UX * Nd + node], T = fd[F_T * Nd + node];
+      uy = fd[F_UY * Nd + node];
+      const double nu0 = fd[F_NU * Nd + node];
+      nu = j0 ? nu0 : 0.0;
+      const double pre = j1 ? fd[F_PRE * Nd + node] : 0.0;
+      Fx = fd[F_FX * Nd + node];
+      Fy = fd[F_FY * Nd + node];
+      const double invT = 1.0 / T;
+      const double tf = d == 0 ? 1.0 : 0.5 * T;
+      const double th0 = d == 0 ? 4.0 : 2.0;
+      const double uxx = fd[F_UXX * Nd + node], uyy = fd[F_UYY * Nd + node];
+      const double Sx = nu * fd[F_SQX * Nd + node] + 0.3 * pre * fd[F_BX * Nd + node];
+      const double Sy = nu * fd[F_SQY * Nd + node] + 0.3 * pre * fd[F_BY * Nd + node];
+      const double C = 0.2 * pre * (uxx + uyy);
+      const double W4 = 0.4 * pre * invT;
+      const double pAx = pre * fd[F_AX * Nd + node], pAy = pre * fd[F_AY * Nd + node];
+      const double Uc = W4 * (fd[F_UXY * Nd + node] + fd[F_UYX * Nd + node]);
+      de = invT * Sy;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const double xx = pkv[j] - ux;
+        const double t0 = xx * xx * invT - th0;
+        const double r = xx * Sx + C;
+        al[j] = nu + pAx * xx + t0 * r + W4 * uxx * xx * xx;
+        be[j] = pAy + t0 * Sy + Uc * xx;
+        ga[j] = invT * r + W4 * uyy;
+        ne[j] = tf * n * ex[j];
+      }
+      if (!j0 && !j1) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) ne[j] = 0.0;
+      }
+    }
+    // velocity sums of the new state: 1, p_x, p_y (both passes), p_x^2,
+    // p_x p_y, p_y^2, p_x |p|^2, p_y |p|^2 (used for F only)
+    double S[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     // fully unrolled: every M[j][l] index is static, M stays in registers
 #pragma unroll
     for (int l = 0; l < Q; ++l) {
+      double wcur[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) wcur[j] = wb[l % PF][j];
+      if (l + PF < Q) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) wb[l % PF][j] = bload(PLANE(wd, j, l + PF), vo);
+      }
       dbl4 acc = {0.0, 0.0, 0.0, 0.0};
-      if (frc) {
+      if (FRC) {
         acc = __builtin_amdgcn_mfma_f64_16x16x4f64(aop[0], M[0][l], acc, 0, 0, 0);
         acc = __builtin_amdgcn_mfma_f64_16x16x4f64(aop[1], M[1][l], acc, 0, 0, 0);
         acc = __builtin_amdgcn_mfma_f64_16x16x4f64(aop[2], M[2][l], acc, 0, 0, 0);
         acc = __builtin_amdgcn_mfma_f64_16x16x4f64(aop[3], M[3][l], acc, 0, 0, 0);
       }
       const double pl = vl[l];
-      const double xy = pl - uy_d;
-      const double eyl = ey[l];
+      const double xy = pl - uy;
+      const double eyl = eyv[l];
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const double f = M[j][l];
-        const double pk = pkv[j];
-        const double xx = pk - ux_d;
-        const double th = (xx * xx + xy * xy) * it_d;
-        const double E = n_d * ex[j] * eyl;
-        double R = 0.0;
-        if (frc) {
+        double R = ne[j] * eyl * (al[j] + xy * (be[j] + xy * (ga[j] + de * xy))) - nu * M[j][l];
+        if (FRC) {
           double d0 = 0.0, d1 = 0.0;
 #pragma unroll
           for (int l2 = 0; l2 < Q; l2 += 2) {
             d0 += dp[l * Q + l2] * M[j][l2];
             d1 += dp[l * Q + l2 + 1] * M[j][l2 + 1];
           }
-          R -= fl[F_FX] * acc[j] + fl[F_FY] * (d0 + d1);
+          R -= Fx * acc[j] + Fy * (d0 + d1);
         }
-        if (j0) {
-          const double fS = tf * E * (1.0 + (xx * fl[F_SQX] + xy * fl[F_SQY]) * (th - th0));
-          R -= fl[F_NU] * (f - fS);
-        }
-        if (j1) {
-          const double xA = xx * fl[F_AX] + xy * fl[F_AY];
-          const double xB = xx * fl[F_BX] + xy * fl[F_BY];
-          const double xxu = (xx * xx * fl[F_UXX] + xx * xy * fl[F_UXY] + xy * xx * fl[F_UYX] +
-                              xy * xy * fl[F_UYY]) * it_d;
-          R += fl[F_PRE] * tf * E * (xA + 0.3 * (th - th0) * xB + 0.4 * (xxu + 0.5 * (th - th0) * div));
-        }
-        const long long o = (long long)((g + 4 * j) * Q + l) * N;
-        const double out = wio[o] + A.c * R;
-        if (valid) wio[o] = out;
-        if (d == 0) {
-          const double p2 = pk * pk + pl * pl;
-          m.n += out;
-          m.jx += pk * out;
-          m.jy += pl * out;
-          m.pxx += pk * pk * out;
-          m.pxy += pk * pl * out;
-          m.pyy += pl * pl * out;
-          m.rx += pk * p2 * out;
-          m.ry += pl * p2 * out;
-        } else {
-          m.g0 += out;
-          m.hx += pk * out;
-          m.hy += pl * out;
-        }
+        const double out = wcur[j] + A.c * R;
+        bstore(out, PLANE(wd, j, l), vs);
+        const double pk = pkv[j];
+        const double a1 = pk * out, a2 = pl * out;
+        const double p2 = pk * pk + pl * pl;
+        S[0] += out;
+        S[1] += a1;
+        S[2] += a2;
+        S[3] += pk * a1;
+        S[4] += pl * a1;
+        S[5] += pl * a2;
+        S[6] += p2 * a1;
+        S[7] += p2 * a2;
       }
-      // keep the scheduler from hoisting the W loads of later columns
+      // one column at a time: keeps later columns' work from being hoisted
       __builtin_amdgcn_sched_barrier(0);
+    }
+#undef PLANE
+    if (d == 0) {
+      m.n = S[0]; m.jx = S[1]; m.jy = S[2]; m.pxx = S[3]; m.pxy = S[4]; m.pyy = S[5]; m.rx = S[6]; m.ry = S[7];
+    } else {
+      m.g0 = S[0]; m.hx = S[1]; m.hy = S[2];
     }
   }
   if (!A.want_mom) return;
@@ -604,7 +689,7 @@ int validate(const evlb_params* p) {
   if (p->n_sys != 1 || !p->nx) return EVLB_EINVAL;
   if (p->nx[0] < 8 || p->ny < 8) return EVLB_EINVAL;
   const long long N = (long long)p->nx[0] * p->ny;
-  if (N > (1ll << 30)) return EVLB_EINVAL;
+  if (N > (1ll << 22)) return EVLB_EINVAL;  // 32-bit buffer offsets of the velocity kernel
   if (p->q != Q) return EVLB_EUNSUPPORTED;
   if (!(p->dx > 0) || !(p->dt > 0) || !std::isfinite(p->dx) || !std::isfinite(p->dt)) return EVLB_EINVAL;
   if (!(p->sigma > 0) || !std::isfinite(p->sigma) || !(p->phi_sigma >= 0) || !std::isfinite(p->phi_sigma))
@@ -736,14 +821,23 @@ int launch_fields(Ctx* c, hipStream_t st) {
 }
 
 int launch_adv(Ctx* c, const AdvArgs& A, hipStream_t st) {
-  const long long nb = (long long)((c->nx + ATX - 1) / ATX) * ((c->ny + ATY - 1) / ATY) * 2 * V;
+  if (!(c->dev.term_mask & EVLB_TERM_ADV)) {
+    const long long nb = (2 * V * c->N + 255) / 256;
+    hipLaunchKernelGGL(combine_kernel, dim3((unsigned)nb), dim3(256), 0, st, c->dev, A);
+    return launched();
+  }
+  const long long strips = (long long)((c->nx + AW - 1) / AW) * ((c->ny + AR - 1) / AR) * 2 * V;
+  const long long nb = (strips + 3) / 4;
   hipLaunchKernelGGL(adv_kernel, dim3((unsigned)nb), dim3(ANT), 0, st, c->dev, A, c->vel);
   return launched();
 }
 
 int launch_vel(Ctx* c, const VelArgs& A, hipStream_t st) {
   const unsigned nb = (unsigned)(((c->nx + 63) / 64) * c->ny);
-  hipLaunchKernelGGL(vel_kernel, dim3(nb), dim3(256), 0, st, c->dev, A, c->vel, c->meq, c->dpm);
+  if (c->dev.term_mask & EVLB_TERM_FORCE)
+    hipLaunchKernelGGL(vel_kernel<true>, dim3(nb), dim3(256), 0, st, c->dev, A, c->vel, c->meq, c->dpm);
+  else
+    hipLaunchKernelGGL(vel_kernel<false>, dim3(nb), dim3(256), 0, st, c->dev, A, c->vel, c->meq, c->dpm);
   return launched();
 }
 
