@@ -6,9 +6,11 @@ velocities, dx = sigma/8, liquid slab 64 sigma wide (eq:tan) at the
 coexistence densities of T/T_c = 0.8.  The metric counts site-velocity
 updates per second: nodes x velocities x 3 stages x steps / GPU time.
 
-A secondary entry reports the batched sweep (512 independent periodic systems
-of log-uniform length in [256, 8192], Q = 16, about 1.1M nodes), the
-HBM-sized case, with its own roofline.
+Secondary entries report the batched sweep (512 independent periodic systems
+of log-uniform length in [256, 8192], Q = 16, about 1.1M nodes) and the 2D
+phase separation (1024 x 1024 nodes, 16 x 16 velocities, 2.7e8
+site-velocities), the HBM-sized cases, each with its own roofline, and the
+adjoint/forward time ratio of the differentiable slab workload.
 
 Prints one JSON line.  The state is resident in HBM before the timed region;
 timing uses HIP events on the stream the kernels run on.  The launch shape of
@@ -65,19 +67,22 @@ def cpu_baseline(c, n, u, T, target_s=15.0):
 
 def measured_traffic(workload, kernel):
     """HBM bytes per launch from the committed counter runs (profiles/
-    hbm_traffic.txt), or None when the kernel source changed since."""
+    hbm_traffic.txt), or None when the kernel's source file changed since."""
     import hashlib
     try:
         with open(os.path.join(ROOT, "profiles", "hbm_traffic.txt")) as fh:
             rec = json.load(fh)
-        with open(os.path.join(ROOT, rec["source"]), "rb") as fh:
+        e = rec["entries"].get(f"{workload}/{kernel}")
+        if e is None:
+            return None
+        src = e.get("source", rec.get("source"))
+        with open(os.path.join(ROOT, src), "rb") as fh:
             sha = hashlib.sha256(fh.read()).hexdigest()
     except (OSError, ValueError, KeyError):
         return None
-    if sha != rec.get("source_sha256"):
+    if sha != e.get("source_sha256", rec.get("source_sha256")):
         return None
-    e = rec["entries"].get(f"{workload}/{kernel}")
-    return None if e is None else e["bytes_per_launch"]
+    return e["bytes_per_launch"]
 
 
 def default_tile(nx, cus=256):
@@ -130,6 +135,51 @@ def measure(E, torch, dev, q, dx, dt, nx, n, u, T, steps, warmup, mode=None, til
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "bytes_per_launch": alg_bytes, "avg_launch_us": gpu_s / launches * 1e6},
     }
+
+
+KERNELS_2D = ("fields_kernel", "adv_kernel", "vel_kernel<true>")
+
+
+def measure_2d(E, torch, dev, steps, warmup):
+    """2D phase separation: 1024 x 1024 periodic nodes, dx = sigma/4, 16 x 16
+    tensor Gauss-Hermite velocities plus the reduced z-energy, T = 0.75 T_c
+    of the disc kernel, n0 = 0.3 with 1% Gaussian noise.  One RK stage is three
+    launches (node fields, advection, velocity space); the roofline is taken
+    over the stage: algorithmic bytes per stage / stage time."""
+    import workloads
+    c, n, ux, uy, T = workloads.phase_separation_2d()
+    td = lambda a: torch.tensor(a, dtype=torch.float64, device=dev)
+    s = E.Solver(c["Q"], c["dx"], c["dt"], c["nx"], ny=c["ny"], device=dev)
+    f = s.equilibrium(td(n), td(np.stack([ux, uy])), td(T))
+    stream = torch.cuda.current_stream()
+    if warmup:
+        s.step(f, warmup)
+    torch.cuda.synchronize()
+    if s.status() != 0:
+        raise RuntimeError("non-finite 2D state during warm-up")
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    s.step(f, steps)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    gpu_s = ev0.elapsed_time(ev1) / 1e3
+    if s.status() != 0:
+        raise RuntimeError("device status not ok after the timed 2D run")
+    n_tot = c["nx"] * c["ny"]
+    nvel = c["Q"] * c["Q"]
+    stage_s = gpu_s / (3 * steps)
+    alg_stage = BYTES_PER_UPDATE_STEP / 3 * n_tot * nvel
+    achieved = alg_stage / stage_s / 1e9
+    traffic = [measured_traffic("phase_separation_2d", k) for k in KERNELS_2D]
+    return {"config": {"workload": "phase_separation_2d", "nx": c["nx"], "ny": c["ny"], "q": f"{c['Q']}x{c['Q']}",
+                       "dx": c["dx"], "dt": c["dt"], "T": c["T"]},
+            "steps": steps, "value": n_tot * nvel * 3 * steps / gpu_s, "unit": "updates/s",
+            "ms_per_step": gpu_s * 1e3 / steps,
+            "roofline": {"bound": "hbm", "kernel": "stage = " + " + ".join(KERNELS_2D), "achieved": achieved,
+                         "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                         "traffic": None if None in traffic else sum(traffic),
+                         "bytes_per_stage": alg_stage, "avg_stage_us": stage_s * 1e6}}
 
 
 def adjoint_ratio(E, torch, dev, nsteps):
@@ -185,6 +235,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-2d", action="store_true")
+    ap.add_argument("--steps-2d", type=int, default=10)
     ap.add_argument("--adjoint-steps", type=int, default=2000)
     ap.add_argument("--no-autotune", action="store_true",
                     help="use the library's default launch shape (one kernel per stage) instead of timing candidates")
@@ -242,6 +294,8 @@ def main():
                        "dx": cb["dx"], "exec": mb["exec"], "tile_nodes": mb["tile_nodes"]},
             "steps": args.batch_steps, "value": mb["value"], "unit": "updates/s", "ms_per_step": mb["ms_per_step"],
             "roofline": dict(mb["roofline"], traffic=measured_traffic("batched_sweep_1d", mb["roofline"]["kernel"]))}]
+    if not args.no_2d:
+        out["secondary"] = out.get("secondary", []) + [measure_2d(E, torch, dev, args.steps_2d, 1)]
     if not args.no_adjoint:
         out["secondary"] = out.get("secondary", []) + [adjoint_ratio(E, torch, dev, args.adjoint_steps)]
     if args.calibrate_copy:
