@@ -216,11 +216,34 @@ def adjoint_ratio(E, torch, dev, nsteps):
     t4 = time.perf_counter()
     if s.status() != 0:
         raise RuntimeError("device status not ok in the adjoint workload")
+    # the transposed step alone: evlb_adjoint_record over a recorded segment
+    # (no recomputation) against evlb_step, per step, on HIP events
+    seg = int(np.ceil(np.sqrt(nsteps)))
+    reps = max(1, nsteps // seg)
+    rec = s.record_buffer(seg)
+    s.step_record(f, seg, rec)
+    lam0 = torch.full_like(f, 1e-3)
+    lam = lam0.clone()
+    dpar = torch.zeros(2, dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream()
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    s.adjoint_record(rec, seg, lam, dpar)
+    e[0].record(stream)
+    for _ in range(reps):
+        s.adjoint_record(rec, seg, lam, dpar)
+    e[1].record(stream)
+    e[2].record(stream)
+    s.step(f, reps * seg)
+    e[3].record(stream)
+    torch.cuda.synchronize()
+    adj_step = e[0].elapsed_time(e[1]) / (reps * seg)
+    fwd_step = e[2].elapsed_time(e[3]) / (reps * seg)
     return {"config": {"workload": "adjoint_slab_1d", "nx": c["nx"], "q": c["Q"], "dx": c["dx"], "steps": nsteps,
                        "checkpoint_every": int(np.ceil(np.sqrt(nsteps)))},
             "metric": "adjoint/forward time", "value": (t2 - t1) / (t1 - t0), "unit": "ratio",
             "forward_s": t1 - t0, "backward_s": t2 - t1, "plain_forward_s": t4 - t3,
             "ratio_vs_plain_forward": (t2 - t1) / (t4 - t3),
+            "adjoint_step_ms": adj_step, "forward_step_ms": fwd_step, "adjoint_step_over_forward_step": adj_step / fwd_step,
             "grad": {"dL_dphi": g[1].item(), "dL_dsigma": g[2].item(), "dL_dn0_norm": g[0].norm().item()}}
 
 
