@@ -25,6 +25,10 @@ class Params:
     r_cut: absolute truncation radius of the attractive kernel (the paper
     gives none; 5 sigma is used).  term_mask / g_ext are test switches:
     g_ext is a uniform external force added to the Vlasov force.
+    T_iso > 0 selects the isothermal runs of Sec. III A, where the fluid
+    temperature is kept constant: the node temperature every kinetic term
+    sees (equilibrium, Shakhov, transport, J1) is T_iso instead of the
+    moment of f, so grad T = 0.  T_iso = 0 is the thermal model.
     """
     Q: int
     dx: float
@@ -38,6 +42,7 @@ class Params:
     weno_eps: float = 1e-6
     g_ext: float = 0.0
     sigma_ref: float = field(default=None)  # fixes the node windows
+    T_iso: float = 0.0
 
     def __post_init__(self):
         if self.sigma_ref is None:

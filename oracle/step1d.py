@@ -208,6 +208,8 @@ def node_fields(F, G, tb: Tables):
     """All per-node quantities the kinetic terms need at one stage."""
     p = tb.p
     n, u, T, q = moments(F, G, tb)
+    if p.T_iso:
+        T = np.full_like(T, p.T_iso)
     nbar = averaged_density(n, tb)
     chi = model.contact_value(nbar, p.sigma)
     Fx = vlasov_force(n, tb)

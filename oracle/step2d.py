@@ -171,6 +171,8 @@ def equilibrium(n, ux, uy, T, tb):
 def node_fields(F, G, tb):
     p = tb.p
     n, ux, uy, T, qx, qy = moments(F, G, tb)
+    if p.T_iso:
+        T = np.full_like(T, p.T_iso)
     nbar = averaged_density(n, tb)
     chi = model.contact_value(nbar, p.sigma)
     Fx, Fy = vlasov_force(n, tb)

@@ -381,3 +381,20 @@ def test_uniform_external_force_2d():
     n, ux, uy, T, qx, qy = step2d.moments(F1, G1, tb)
     assert np.allclose(ux, 0.2 * 20 * 0.01, rtol=1e-12)
     assert np.max(np.abs(uy)) < 1e-14 and np.allclose(T, 0.6, rtol=1e-12)
+
+
+def test_isothermal_2d_rhs_equals_thermal_at_uniform_temperature():
+    """2D isothermal mode: with the moment temperature uniform and equal to
+    T_iso the right-hand side is the thermal one."""
+    tb = step2d.Tables2D(Params(Q=8, dx=0.25, dt=_dt(0.25)))
+    tbi = step2d.Tables2D(Params(Q=8, dx=0.25, dt=_dt(0.25), T_iso=0.6))
+    rng = np.random.default_rng(4)
+    N = 12
+    n = 0.3 * (1 + 0.05 * rng.standard_normal((N, N)))
+    ux = 0.03 * rng.standard_normal((N, N))
+    uy = 0.03 * rng.standard_normal((N, N))
+    F, G = step2d.initial_state(n, ux, uy, np.full((N, N), 0.6), tb)
+    LF, LG = step2d.rhs(F, G, tb)
+    LFi, LGi = step2d.rhs(F, G, tbi)
+    assert np.max(np.abs(LFi - LF)) < 1e-12 * np.max(np.abs(LF))
+    assert np.max(np.abs(LGi - LG)) < 1e-12 * np.max(np.abs(LG))

@@ -656,3 +656,60 @@ def test_ev2_force_on_sinusoid():
     got = step1d.vlasov_force(np.cos(k * x), tb)
     ref = (-2 * (4 * np.pi / 3) * k + (4 * np.pi / 5) * k ** 3) * np.sin(k * x)
     assert np.max(np.abs(got - ref)) < 1e-3 * np.max(np.abs(ref))
+
+
+# ---------------------------------------------------------------------------
+# isothermal mode (Sec. III A keeps the fluid temperature constant)
+# ---------------------------------------------------------------------------
+
+def test_isothermal_energy_relaxes_to_fixed_temperature():
+    """Uniform state at T0 != T_iso: only J0 acts, relaxing the energy
+    e = sum(xi^2/2 F + G) towards 3/2 n T_iso at the rate nu(n, T_iso);
+    one TVD-RK3 step multiplies e - 3/2 n T_iso by R(-nu dt)."""
+    n0, T0, Tiso = 0.4, 0.75, 0.6
+    p = Params(Q=16, dx=1 / 8, dt=0.05, T_iso=Tiso)
+    tb = step1d.Tables(p)
+    F, G = step1d.initial_state(np.full(8, n0), 0.0, T0, tb)
+    m = step1d.node_fields(F, G, tb)
+    nu = m["nu"][0]
+    assert abs(nu - model.collision_rate(n0, Tiso, m["chi"][0], 1.0)) < 1e-15 * nu
+    v = tb.v[:, None]
+    e = lambda F, G: (0.5 * v ** 2 * F + G).sum(0)[0]
+    R = lambda z: 1 + z + z * z / 2 + z ** 3 / 6
+    F1, G1 = step1d.rk3_step(F, G, tb)
+    eiso = 1.5 * n0 * Tiso
+    assert abs((e(F1, G1) - eiso) / (e(F, G) - eiso) - R(-nu * p.dt)) < 1e-12
+    n1, u1, T1, q1 = step1d.moments(F1, G1, tb)
+    assert np.allclose(n1, n0, rtol=1e-14) and np.max(np.abs(u1)) < 1e-15
+
+
+def test_isothermal_rhs_equals_thermal_rhs_at_uniform_temperature():
+    """Where the moment temperature is uniform and equal to T_iso, the
+    isothermal right-hand side is the thermal one (the fixed temperature
+    replaces exactly the moment temperature)."""
+    F, G, tb = _random_state(amp=0.0)
+    N = F.shape[1]
+    x = np.arange(N) / N
+    n = 0.3 * (1 + 0.05 * np.sin(2 * np.pi * x))
+    u = 0.04 * np.cos(2 * np.pi * x)
+    F, G = step1d.initial_state(n, u, np.full(N, 0.6), tb)
+    LF, LG = step1d.rhs(F, G, tb)
+    tbi = step1d.Tables(Params(Q=16, dx=tb.p.dx, dt=tb.p.dt, T_iso=0.6))
+    LFi, LGi = step1d.rhs(F, G, tbi)
+    assert np.max(np.abs(LFi - LF)) < 1e-12 * np.max(np.abs(LF))
+    assert np.max(np.abs(LGi - LG)) < 1e-12 * np.max(np.abs(LG))
+
+
+def test_isothermal_stationary_and_conservation():
+    """A uniform Maxwellian at T_iso stays put; a non-uniform state keeps its
+    mass and momentum (energy is not conserved at fixed temperature)."""
+    p = Params(Q=16, dx=1 / 8, dt=0.2 / 8 / 6.6308782, T_iso=0.6)
+    tb = step1d.Tables(p)
+    F, G = step1d.initial_state(np.full(32, 0.3), 0.0, 0.6, tb)
+    F1, G1 = step1d.run(F, G, tb, 20)
+    assert np.max(np.abs(F1 - F)) <= 1e-14 * np.max(F)
+    F, G, _ = _random_state()
+    v = tb.v[:, None]
+    F1, G1 = step1d.run(F, G, tb, 5)
+    assert abs(F1.sum() - F.sum()) < 1e-13 * F.sum()
+    assert abs((v * F1).sum() - (v * F).sum()) < 1e-13 * np.sum(np.abs(v) * F)
