@@ -51,7 +51,7 @@
 extern "C" {
 #endif
 
-#define EVLB_ABI_VERSION 2
+#define EVLB_ABI_VERSION 3
 
 enum {
   EVLB_OK = 0,
@@ -112,6 +112,13 @@ typedef struct {
   int32_t tile_nodes;    /* nodes per workgroup tile: 0 = auto, 16, 63 or 64 */
   int32_t adjoint;       /* 1: size the workspace for evlb_adjoint_step      */
   int32_t ny;            /* dim 2: nodes along y (>= 8); ignored for dim 1   */
+  double T_iso;          /* > 0: isothermal run at this temperature, as in
+                            the stationary-interface runs of Sec. III A
+                            where T is kept constant: every kinetic term
+                            (equilibrium, Shakhov, transport, J1) uses T_iso
+                            instead of the moment temperature, so grad T = 0
+                            and the energy is not conserved.  0: the thermal
+                            model.  Not available with adjoint = 1.          */
 } evlb_params;
 
 typedef struct evlb_ctx evlb_ctx; /* opaque, host memory */
@@ -155,7 +162,8 @@ int evlb_step(evlb_ctx* ctx, double* d_f, int32_t nsteps, void* hip_stream);
 int evlb_rhs(evlb_ctx* ctx, const double* d_f, double* d_L, void* hip_stream);
 
 /* Moments of d_f (Sec. II B): n = sum F, n u = sum p F,
- * 3/2 n T = sum (xi^2/2 F + G), q = sum xi (xi^2/2 F + G), xi = p - u.
+ * 3/2 n T = sum (xi^2/2 F + G), q = sum xi (xi^2/2 F + G), xi = p - u
+ * (T is the moment temperature also in isothermal runs).
  * Outputs device [n_tot]; d_q may be NULL.  dim 2: xi is the in-plane
  * peculiar velocity and d_u, d_q are [2][n_tot]. */
 int evlb_moments(evlb_ctx* ctx, const double* d_f, double* d_n, double* d_u,

@@ -60,6 +60,7 @@ struct DevParams {
   double mu0c;     // 5 / (16 sigma^2 sqrt(pi)):  mu0 = mu0c sqrt(T)
   double sigma;
   double weno_eps, g_ext, two_a, kappa;
+  double T_iso;    // > 0: isothermal, the temperature the next stage sees
   int force_model, term_mask;
   int* status;     // [0] non-finite latch, [1] barrier abort latch
   unsigned* bar;   // [0] arrival count, [1] generation
@@ -419,7 +420,7 @@ __device__ void stage_tile(const DevParams& P, const StageArgs& A, int tile, Sme
     const double q = 0.5 * x3 + S.msum[5][tid] - u * S.msum[4][tid];
     A.mom_out[gnode] = n;
     A.mom_out[ntot + gnode] = u;
-    A.mom_out[2 * ntot + gnode] = T;
+    A.mom_out[2 * ntot + gnode] = P.T_iso > 0.0 ? P.T_iso : T;
     A.mom_out[3 * ntot + gnode] = q;
     if (!(n > 0.0) || !(T > 0.0) || !isfinite(n) || !isfinite(T) || !isfinite(q) || !isfinite(u))
       P.status[0] = 1;
@@ -655,7 +656,7 @@ __device__ void stage_tile_col(const DevParams& P, const StageArgs& A, int tile,
     const double q1 = 0.5 * x3 + pm[5] - u1 * pm[4];
     A.mom_out[gnode] = n1;
     A.mom_out[ntot + gnode] = u1;
-    A.mom_out[2 * ntot + gnode] = T1;
+    A.mom_out[2 * ntot + gnode] = P.T_iso > 0.0 ? P.T_iso : T1;
     A.mom_out[3 * ntot + gnode] = q1;
     if (!(n1 > 0.0) || !(T1 > 0.0) || !isfinite(n1) || !isfinite(T1) || !isfinite(q1) || !isfinite(u1))
       P.status[0] = 1;
@@ -782,7 +783,8 @@ __global__ __launch_bounds__(SHAPE::NT) void persistent_kernel(DevParams P, Pers
 template <int Q>
 __global__ __launch_bounds__(256) void moments_kernel(DevParams P, const double* __restrict__ f,
                                                       double* __restrict__ n_out, double* __restrict__ u_out,
-                                                      double* __restrict__ T_out, double* __restrict__ q_out) {
+                                                      double* __restrict__ T_out, double* __restrict__ q_out,
+                                                      int stage_input) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= P.ntot) return;
   const long long nt = P.ntot;
@@ -807,7 +809,8 @@ __global__ __launch_bounds__(256) void moments_kernel(DevParams P, const double*
   const double T = (2.0 / 3.0) * e / n;
   n_out[i] = n;
   u_out[i] = u;
-  T_out[i] = T;
+  // as the input of a stage, an isothermal run sees its fixed temperature
+  T_out[i] = stage_input && P.T_iso > 0.0 ? P.T_iso : T;
   if (q_out) q_out[i] = q;
 }
 
@@ -892,6 +895,8 @@ int validate(const evlb_params* p) {
   if (p->exec_mode < 0 || p->exec_mode > 2) return EVLB_EINVAL;
   if (p->adjoint != 0 && p->adjoint != 1) return EVLB_EINVAL;
   if (p->adjoint && p->force_model == EVLB_FORCE_EV2) return EVLB_EUNSUPPORTED;
+  if (!(p->T_iso >= 0.0) || !std::isfinite(p->T_iso)) return EVLB_EINVAL;
+  if (p->adjoint && p->T_iso > 0.0) return EVLB_EUNSUPPORTED;
   if (p->tile_nodes != 0 && p->tile_nodes != WIDE && p->tile_nodes != NARROW && p->tile_nodes != WC)
     return EVLB_EINVAL;
   int ms, mf = 0;
@@ -1036,10 +1041,11 @@ int launch_persistent(evlb_ctx* c, int width, double* f, int nsteps, hipStream_t
 }
 
 template <int Q>
-int run_moments(evlb_ctx* c, const double* f, double* n, double* u, double* T, double* q, hipStream_t st) {
+int run_moments(evlb_ctx* c, const double* f, double* n, double* u, double* T, double* q, hipStream_t st,
+                int stage_input = 1) {
   const long long nt = c->L.ntot;
   const int blocks = (int)((nt + 255) / 256);
-  hipLaunchKernelGGL((moments_kernel<Q>), dim3(blocks), dim3(256), 0, st, c->dp, f, n, u, T, q);
+  hipLaunchKernelGGL((moments_kernel<Q>), dim3(blocks), dim3(256), 0, st, c->dp, f, n, u, T, q, stage_input);
   return hipGetLastError() == hipSuccess ? EVLB_OK : EVLB_EHIP;
 }
 
@@ -1428,6 +1434,7 @@ int evlb_init(const evlb_params* params, void* d_workspace, size_t ws_bytes, voi
   d.kappa = (2.0 * M_PI * std::pow(sg, 5) / 15.0) * params->phi_sigma * (g > 5.0 ? g / (g - 5.0) : 0.0);
   d.force_model = params->force_model;
   d.term_mask = params->term_mask;
+  d.T_iso = params->T_iso;
   d.status = (int*)(c->ws + L.status);
   d.bar = (unsigned*)(c->ws + L.status + 64);
   *out = c;
@@ -1462,7 +1469,7 @@ int evlb_moments(evlb_ctx* ctx, const double* d_f, double* d_n, double* d_u, dou
   if (!ctx || !d_f || !d_n || !d_u || !d_T) return EVLB_EINVAL;
   if (!device_matches(ctx)) return EVLB_EINVAL;
   if (ctx->c2) return evlb2d::moments(ctx->c2, d_f, d_n, d_u, d_T, d_q, (hipStream_t)hip_stream);
-  EVLB_DISPATCH_Q(ctx->p.q, run_moments, ctx, d_f, d_n, d_u, d_T, d_q, (hipStream_t)hip_stream);
+  EVLB_DISPATCH_Q(ctx->p.q, run_moments, ctx, d_f, d_n, d_u, d_T, d_q, (hipStream_t)hip_stream, 0);
 }
 
 int evlb_adjoint_step(evlb_ctx* ctx, const double* d_f_n, const double* d_lam_np1, double* d_lam_n,

@@ -53,6 +53,7 @@ struct Dev {
   double eta_c;  // pi sigma^3 / 6
   double mu0c;   // 5 / (16 sigma^2 sqrt(pi))
   double weno_eps, g_ext;
+  double T_iso;  // > 0: isothermal, the temperature the next stage sees
   int force_model, term_mask;
   int navg, npair, halo;
   int* status;
@@ -90,7 +91,7 @@ struct Raw {
 };
 
 __device__ __forceinline__ void finish_moments(const Raw& m, double* out6, long long N, long long node,
-                                               int* status) {
+                                               int* status, double T_iso) {
   const double n = m.n;
   const double ux = m.jx / n, uy = m.jy / n;
   const double u2 = ux * ux + uy * uy;
@@ -101,7 +102,7 @@ __device__ __forceinline__ void finish_moments(const Raw& m, double* out6, long 
   out6[node] = n;
   out6[N + node] = ux;
   out6[2 * N + node] = uy;
-  out6[3 * N + node] = T;
+  out6[3 * N + node] = T_iso > 0.0 ? T_iso : T;
   out6[4 * N + node] = qx;
   out6[5 * N + node] = qy;
   if (!(n > 0.0) || !(T > 0.0) || !isfinite(n) || !isfinite(T) || !isfinite(ux) || !isfinite(uy) ||
@@ -113,7 +114,7 @@ __device__ __forceinline__ void finish_moments(const Raw& m, double* out6, long 
 // moments of a state (first stage of a step, evlb_moments)
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void moments_kernel(Dev D, const double* __restrict__ f, double* __restrict__ out6,
-                                                      const double* __restrict__ vel) {
+                                                      const double* __restrict__ vel, int stage_input) {
   const long long node = (long long)blockIdx.x * 256 + threadIdx.x;
   if (node >= D.ntot) return;
   const long long N = D.ntot;
@@ -140,7 +141,8 @@ __global__ __launch_bounds__(256) void moments_kernel(Dev D, const double* __res
       m.hy += pl * G;
     }
   }
-  finish_moments(m, out6, N, node, D.status);
+  // as the input of a stage, an isothermal run sees its fixed temperature
+  finish_moments(m, out6, N, node, D.status, stage_input ? D.T_iso : 0.0);
 }
 
 // Hermite equilibrium of one velocity component at unit density:
@@ -623,7 +625,7 @@ __global__ __launch_bounds__(256) void vel_kernel(Dev D, VelArgs A, const double
   EVLB2D_REDUCE(m.pxy); EVLB2D_REDUCE(m.pyy); EVLB2D_REDUCE(m.rx); EVLB2D_REDUCE(m.ry);
   EVLB2D_REDUCE(m.g0); EVLB2D_REDUCE(m.hx); EVLB2D_REDUCE(m.hy);
 #undef EVLB2D_REDUCE
-  if (valid && g == 0) finish_moments(m, A.mom, N, node, D.status);
+  if (valid && g == 0) finish_moments(m, A.mom, N, node, D.status, D.T_iso);
 }
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -704,6 +706,7 @@ int validate(const evlb_params* p) {
   if (p->tile_nodes != 0) return EVLB_EINVAL;
   if (p->adjoint != 0 && p->adjoint != 1) return EVLB_EINVAL;
   if (p->adjoint) return EVLB_EUNSUPPORTED;
+  if (!(p->T_iso >= 0.0) || !std::isfinite(p->T_iso)) return EVLB_EINVAL;
   if ((int)std::ceil(p->sigma / p->dx) + 2 > HMAX) return EVLB_EINVAL;
   if (p->force_model == EVLB_FORCE_EV1) {
     int mf;
@@ -789,6 +792,7 @@ int init(const evlb_params* p, char* ws, size_t bytes, Ctx** out) {
   d.g_ext = p->g_ext;
   d.force_model = p->force_model;
   d.term_mask = p->term_mask;
+  d.T_iso = p->T_iso;
   d.navg = L.navg;
   d.npair = p->force_model == EVLB_FORCE_EV1 ? L.npair : 0;
   d.halo = L.halo;
@@ -806,9 +810,9 @@ namespace {
 
 int launched() { return hipGetLastError() == hipSuccess ? EVLB_OK : EVLB_EHIP; }
 
-int launch_moments(Ctx* c, const double* f, double* out6, hipStream_t st) {
+int launch_moments(Ctx* c, const double* f, double* out6, hipStream_t st, int stage_input = 1) {
   const unsigned nb = (unsigned)((c->N + 255) / 256);
-  hipLaunchKernelGGL(moments_kernel, dim3(nb), dim3(256), 0, st, c->dev, f, out6, c->vel);
+  hipLaunchKernelGGL(moments_kernel, dim3(nb), dim3(256), 0, st, c->dev, f, out6, c->vel, stage_input);
   return launched();
 }
 
@@ -889,7 +893,7 @@ int rhs(Ctx* c, const double* f, double* L, hipStream_t st) {
 
 int moments(Ctx* c, const double* f, double* n, double* u, double* T, double* q, hipStream_t st) {
   double* m = (double*)(c->ws + c->L.mom);
-  int rc = launch_moments(c, f, m, st);
+  int rc = launch_moments(c, f, m, st, 0);
   if (rc) return rc;
   const size_t nb = sizeof(double) * (size_t)c->N;
   if (hipMemcpyAsync(n, m, nb, hipMemcpyDeviceToDevice, st) != hipSuccess ||

@@ -30,6 +30,7 @@ def test_header_symbols_exported():
 
 def test_validate_accepts_workload_parameters():
     assert P.evlb_validate(P.make_params(16, 0.125, DT16, 256)) == E.EVLB_OK
+    assert P.evlb_validate(P.make_params(16, 0.1, 5e-3, [2000] * 5, T_iso=0.6)) == E.EVLB_OK
     assert P.evlb_validate(P.make_params(24, 0.125, 0.2 * 0.125 / 8.5078, 4096)) == E.EVLB_OK
     assert P.evlb_validate(P.make_params(16, 0.25, 0.2 * 0.25 / 6.6309, [256, 300, 8192])) == E.EVLB_OK
 
@@ -50,6 +51,8 @@ def test_validate_accepts_workload_parameters():
     (dict(weno_eps=0.0), E.EVLB_EINVAL),
     (dict(exec_mode=9), E.EVLB_EINVAL),
     (dict(sigma=-1.0), E.EVLB_EINVAL),
+    (dict(T_iso=-0.5), E.EVLB_EINVAL),
+    (dict(T_iso=0.6, adjoint=1), E.EVLB_EUNSUPPORTED),
 ])
 def test_validate_rejects(kw, code):
     base = dict(q=16, dx=0.125, dt=DT16, nx=256)
@@ -128,6 +131,7 @@ def test_validate_accepts_2d_workload():
     (dict(r_cut=7.0), E.EVLB_EINVAL),       # force disc above the built maximum
     (dict(dt=0.2), E.EVLB_ECFL),
     (dict(dt=0.6 * 0.25 / 6.630878198393129), E.EVLB_ECFL),  # 1D limit met, 2D sum exceeded
+    (dict(T_iso=float("nan")), E.EVLB_EINVAL),
 ])
 def test_validate_rejects_2d(kw, code):
     p = _p2(**kw)
