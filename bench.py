@@ -182,6 +182,46 @@ def measure_2d(E, torch, dev, steps, warmup):
                          "bytes_per_stage": alg_stage, "avg_stage_us": stage_s * 1e6}}
 
 
+def paper_runs(E, torch, dev, steps_3b=None):
+    """The paper's own runs at its parameters (dx = sigma/10, dt = 5e-3,
+    Q = 16), timed end to end for comparison with the single-core runtimes of
+    Table I (context, not a target): Sec. III B, the four phase-separation
+    runs of eq:rho_init_takata to t = 5000 (1e6 steps), and Sec. III C, the
+    four evaporation runs to t = 75 (15000 steps), each set as one batched
+    launch sequence, with EV1 and with EV2."""
+    import workloads
+    td = lambda a: torch.tensor(a, dtype=torch.float64, device=dev)
+    out = []
+    for name, make in (("paper_sec3b_phase_separation", workloads.paper_sec3b),
+                       ("paper_sec3c_evaporation", workloads.paper_sec3c)):
+        c, systems = make()
+        steps = c["steps"] if (steps_3b is None or name.endswith("evaporation")) else steps_3b
+        n = np.concatenate([x[0] for x in systems])
+        u = np.concatenate([x[1] for x in systems])
+        T = np.concatenate([x[2] for x in systems])
+        nxs = [len(x[0]) for x in systems]
+        for fm, label, paper_s in ((E.EVLB_FORCE_EV1, "EV1", c["table1_ev1_s"]),
+                                   (E.EVLB_FORCE_EV2, "EV2", c["table1_ev2_s"])):
+            s = E.Solver(c["Q"], c["dx"], c["dt"], nxs, device=dev, force_model=fm)
+            f = s.equilibrium(td(n), td(u), td(T))
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            s.step(f, steps)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            if s.status() != 0:
+                raise RuntimeError(f"device status not ok in {name} {label}")
+            out.append({"config": {"workload": name, "force": label, "runs": len(systems), "nx": nxs[0],
+                                   "q": c["Q"], "dx": c["dx"], "dt": c["dt"], "steps": steps,
+                                   "t_end": steps * c["dt"]},
+                        "metric": "wall time of the batched runs", "value": wall, "unit": "s",
+                        "higher_is_better": False,
+                        "updates_per_s": sum(nxs) * c["Q"] * 3 * steps / wall,
+                        "paper_single_core_s_per_run": paper_s if steps == c["steps"] else None})
+            del s, f
+    return out
+
+
 def adjoint_ratio(E, torch, dev, nsteps):
     """Adjoint workload: 2048 nodes, dx = sigma/4, Q = 16, slab at T = 0.85
     T_c; loss = time-integrated flux through x = 128 sigma + final misfit.
@@ -259,6 +299,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-2d", action="store_true")
+    ap.add_argument("--paper-runs", action="store_true",
+                    help="also time the paper's own Sec. III B / III C runs at its parameters (about a minute)")
+    ap.add_argument("--paper-3b-steps", type=int, default=None, help="shorten the Sec. III B runs (default: 1e6)")
     ap.add_argument("--steps-2d", type=int, default=10)
     ap.add_argument("--adjoint-steps", type=int, default=2000)
     ap.add_argument("--no-autotune", action="store_true",
@@ -321,6 +364,8 @@ def main():
         out["secondary"] = out.get("secondary", []) + [measure_2d(E, torch, dev, args.steps_2d, 1)]
     if not args.no_adjoint:
         out["secondary"] = out.get("secondary", []) + [adjoint_ratio(E, torch, dev, args.adjoint_steps)]
+    if args.paper_runs:
+        out["secondary"] = out.get("secondary", []) + paper_runs(E, torch, dev, args.paper_3b_steps)
     if args.calibrate_copy:
         x = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device=dev)
         y = torch.empty_like(x)

@@ -51,6 +51,24 @@ def main():
         Q=16, dx=0.25, nx=1024, ny=1024, T=0.75 * tc2d, n0=0.3, noise=0.01, steps=2000, seed=2503154,
         dt=0.2 * 0.25 / vmax[16], a_disc=a2d, Tc_disc=tc2d)
 
+    # the paper's own runs (Sec. III B and III C): dx = sigma/10, dt = 5e-3,
+    # Q = 16, absolute temperatures, a of the discrete kernel at sigma/10
+    a10, tc10 = tc_disc(0.1)
+    pairs = [[0.7, 0.4], [0.65, 0.55], [0.6, 0.65], [0.55, 0.7]]
+    amp = []
+    for T, _ in pairs:
+        nv, nl = model.maxwell_construction(T, a10)
+        amp.append(0.5 * (nl + nv))
+    out["paper_sec3b_phase_separation"] = dict(
+        Q=16, dx=0.1, dt=5e-3, L=100.0, nx=1000, pairs=pairs, A=amp, t_end=5000.0, steps=1000000,
+        a_disc=a10, Tc_disc=tc10, table1_ev1_s=1.8e4, table1_ev2_s=6e3)
+    temps = [0.6, 0.65, 0.7, 0.74]
+    coex = [list(model.maxwell_construction(T, a10)) for T in temps]
+    out["paper_sec3c_evaporation"] = dict(
+        Q=16, dx=0.1, dt=5e-3, nx=4000, x0=25.0, width=2.0, T=temps, n_v=[c[0] for c in coex],
+        n_l=[c[1] for c in coex], t_end=75.0, steps=15000, a_disc=a10, Tc_disc=tc10,
+        table1_ev1_s=3.4e3, table1_ev2_s=9e2)
+
     T5 = 0.85 * tc4
     nv5, nl5 = model.maxwell_construction(T5, a4)
     out["adjoint_slab_1d"] = dict(

@@ -68,6 +68,33 @@ def phase_separation_2d(nx=None, ny=None, seed=None):
     return c, n, z, z.copy(), np.full(shp, c["T"])
 
 
+def paper_sec3b():
+    """The four phase-separation runs of Sec. III B (eq:rho_init_takata):
+    n = A (1 + omega cos(2 pi x / L)) on [-L/2, L/2), L = 100 sigma, at rest,
+    uniform T_i, A = (n_l + n_v)/2 at T_i.  Returns (params dict, list of
+    (n, u, T))."""
+    c = dict(constants()["paper_sec3b_phase_separation"])
+    x = grid(c["nx"], c["dx"])
+    systems = []
+    for (T, omega), A in zip(c["pairs"], c["A"]):
+        n = A * (1.0 + omega * np.cos(2.0 * np.pi * x / c["L"]))
+        systems.append((n, np.zeros(c["nx"]), np.full(c["nx"], T)))
+    return c, systems
+
+
+def paper_sec3c():
+    """The four evaporation runs of Sec. III C: liquid slab (eq:tan) with
+    interfaces at +-25 sigma in [-200 sigma, 200 sigma), vapour at n_v/2,
+    at rest, uniform T_i.  Returns (params dict, list of (n, u, T))."""
+    c = dict(constants()["paper_sec3c_evaporation"])
+    x = grid(c["nx"], c["dx"])
+    systems = []
+    for T, nl, nv in zip(c["T"], c["n_l"], c["n_v"]):
+        n = tanh_slab(x, nl, nv, c["x0"], c["width"])
+        systems.append((n, np.zeros(c["nx"]), np.full(c["nx"], T)))
+    return c, systems
+
+
 def slab_1d(name="slab_evaporation_1d", nx=None, dx=None):
     """Liquid slab (eq:tan) centred in the periodic box, at rest, uniform
     temperature.  nx/dx may be overridden for reduced-size cases (the slab
