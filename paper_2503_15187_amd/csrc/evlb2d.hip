@@ -16,8 +16,9 @@
 //                  (eq:viscosity, eq:tau, eq:prandtl), 4th-order central
 //                  gradients of X = n^2 chi T, T and u along x and y.
 //   adv_kernel     one wavefront per strip of 58 columns x 64 rows of one
-//                  velocity plane, marching down the rows with a register
-//                  window; every WENO-5 face computed once,
+//                  velocity plane, marching down the rows with register
+//                  rings; every WENO-5 face computed once from per-node
+//                  stencil terms that three faces share,
 //                  W = a f^n + b f^(s-1) + c Adv(f^(s-1)).
 //   vel_kernel     16 nodes per wavefront, lanes = (node, group g of four p_x
 //                  rows): d/dp_x as (Dp x I) on the f64 MFMA (the node's 16 x 16
@@ -62,25 +63,6 @@ struct Dev {
 __device__ __forceinline__ int wrap(int i, int n) {
   const int r = i % n;
   return r < 0 ? r + n : r;
-}
-
-// WENO-5 (Jiang & Shu) face value from the upwind-ordered v0..v4; the three
-// nonlinear weights over a common denominator (one division).
-__device__ __forceinline__ double weno5(double v0, double v1, double v2, double v3, double v4, double eps) {
-  const double q0 = (2.0 * v0 - 7.0 * v1 + 11.0 * v2) * (1.0 / 6.0);
-  const double q1 = (-v1 + 5.0 * v2 + 2.0 * v3) * (1.0 / 6.0);
-  const double q2 = (2.0 * v2 + 5.0 * v3 - v4) * (1.0 / 6.0);
-  const double c0 = v0 - 2.0 * v1 + v2, e0 = v0 - 4.0 * v1 + 3.0 * v2;
-  const double c1 = v1 - 2.0 * v2 + v3, e1 = v1 - v3;
-  const double c2 = v2 - 2.0 * v3 + v4, e2 = 3.0 * v2 - 4.0 * v3 + v4;
-  const double b0 = (13.0 / 12.0) * c0 * c0 + 0.25 * e0 * e0;
-  const double b1 = (13.0 / 12.0) * c1 * c1 + 0.25 * e1 * e1;
-  const double b2 = (13.0 / 12.0) * c2 * c2 + 0.25 * e2 * e2;
-  double t0 = eps + b0; t0 *= t0;
-  double t1 = eps + b1; t1 *= t1;
-  double t2 = eps + b2; t2 *= t2;
-  const double w0 = 0.1 * t1 * t2, w1 = 0.6 * t0 * t2, w2 = 0.3 * t0 * t1;
-  return (w0 * q0 + w1 * q1 + w2 * q2) / (w0 + w1 + w2);
 }
 
 // Raw velocity sums of one node -> n, u, T, q (Sec. II B moments with the
@@ -297,14 +279,30 @@ __global__ __launch_bounds__(FNT) void fields_kernel(Dev D, const double* __rest
 // ---------------------------------------------------------------------------
 // advection: one wavefront per strip of 58 columns x AR rows of one plane
 // ---------------------------------------------------------------------------
-// Lane t holds column x0 - 3 + t (t < 64) and marches down the rows with a
-// register window of the six rows y - 2 .. y + 3.  The face between rows y and
-// y + 1 is computed once and reused as the upper face of the next row; the
-// face between columns x - 1 and x is computed by lane t from the row values
-// of lanes t - 3 .. t + 2 (shuffles) and the lane's right face comes from
-// lane t + 1.  Lanes 3 .. 60 produce the 58 outputs.  No LDS, no barrier.
+// WENO-5 (Jiang & Shu) rewritten around stencil centres.  A face between
+// v2 and v3 (v0 .. v4 ordered from the upwind side) combines three
+// candidate parabolas on the triples (v0 v1 v2), (v1 v2 v3), (v2 v3 v4).  In
+// terms of one triple (a, m, b), a on the upwind side, with c = a - 2m + b and
+// g = b - a, the candidate value and four times the smoothness indicator in
+// each of the three roles are
+//   role p (far upwind):  m + 13c/12 + 3g/4,  13c^2/3 + (2c + g)^2
+//   role 0 (centred):     m +   c/12 +  g/4,  13c^2/3 + g^2
+//   role m (downwind):    m +   c/12 -  g/4,  13c^2/3 + (2c - g)^2
+// so every node computes its triple once and three faces share it.  The
+// nonlinear weights 0.1, 0.6, 0.3 over (eps + beta_k)^2 are taken over the
+// common denominator; scaling every beta by 4 and eps with it multiplies all
+// three weights by the same 256, which cancels.  The division is a hardware
+// reciprocal refined by two Newton steps r <- r (2 - d r).
+//
+// Lane t holds column x0 - 3 + t and marches down 64 rows.  Along y the
+// triples of rows y - 1 .. y + 2 and the raw rows y .. y + 3 sit in rings of
+// four registers indexed by row mod 4; the loop is unrolled by four so that
+// every ring index is a constant.  Along x each lane builds the triple of its
+// own column from its neighbours' row values and fetches the two triples it
+// lacks from the lanes that own them; the face on its right comes from lane
+// t + 1.  Lanes 3 .. 60 produce the 58 outputs.  No LDS, no barrier.
 constexpr int AW = 58;   // output columns per wavefront
-constexpr int AR = 64;   // output rows per wavefront
+constexpr int AR = 64;   // output rows per wavefront (a multiple of 4)
 constexpr int ANT = 256; // four strips per workgroup
 
 struct AdvArgs {
@@ -315,8 +313,118 @@ struct AdvArgs {
   int first;         // f0 == fs
 };
 
-__device__ __forceinline__ double face(const double* w, bool pos, double eps) {
-  return pos ? weno5(w[0], w[1], w[2], w[3], w[4], eps) : weno5(w[5], w[4], w[3], w[2], w[1], eps);
+struct Tri {
+  double bp, b0, bm;  // 4 beta in the roles p, 0, m
+  double qp, q0, qm;  // candidate values in the roles p, 0, m
+};
+
+__device__ __forceinline__ Tri tri(double a, double m, double b) {
+  const double c = fma(-2.0, m, a + b);
+  const double g = b - a;
+  const double a4 = (13.0 / 3.0) * c * c;
+  const double u = fma(2.0, c, g), w = fma(2.0, c, -g);
+  const double h = fma(1.0 / 12.0, c, m);
+  Tri t;
+  t.bp = fma(u, u, a4);
+  t.b0 = fma(g, g, a4);
+  t.bm = fma(w, w, a4);
+  t.qp = fma(0.75, g, fma(13.0 / 12.0, c, m));
+  t.q0 = fma(0.25, g, h);
+  t.qm = fma(-0.25, g, h);
+  return t;
+}
+
+// Face value from the triple in role p (bp, qp), role 0 and role m; eps4 = 4 eps.
+__device__ __forceinline__ double face3(double bp, double qp, double b0, double q0, double bm, double qm,
+                                        double eps4) {
+  double t0 = eps4 + bp; t0 *= t0;
+  double t1 = eps4 + b0; t1 *= t1;
+  double t2 = eps4 + bm; t2 *= t2;
+  const double w0 = 0.1 * (t1 * t2), w1 = 0.6 * (t0 * t2), w2 = 0.3 * (t0 * t1);
+  const double num = fma(w2, qm, fma(w1, q0, w0 * qp));
+  const double den = w0 + w1 + w2;
+  double r = __builtin_amdgcn_rcp(den);
+  r = fma(r, fma(-den, r, 1.0), r);
+  r = fma(r, fma(-den, r, 1.0), r);
+  return num * r;
+}
+
+// Oriented triple centred on m with its neighbours lo (lower index) and hi.
+template <bool POS>
+__device__ __forceinline__ Tri tri_dir(double lo, double m, double hi) {
+  return POS ? tri(lo, m, hi) : tri(hi, m, lo);
+}
+
+struct AdvStrip {
+  const double* fs;   // this plane of f^(s-1)
+  const double* f0;   // this plane of f^n
+  double* W;          // this plane of W
+  int nx, ny, xc, yr, y0;
+  bool outcol;
+  double pxi, pyi, eps4;  // p_x / dx, p_y / dx
+  double rw[4];       // raw rows, slot = (row - y0) mod 4
+  Tri ct[4];          // triples of rows, slot = (row - y0) mod 4
+  double fyl;         // face between rows y - 1 and y
+};
+
+// Row y = y0 + r with r = PH (mod 4): load row y + 3, build the triple of row
+// y + 2, the face between rows y and y + 1, the two x faces of row y, update.
+template <bool PX, bool PY, int PH>
+__device__ __forceinline__ void adv_row(AdvStrip& S, const AdvArgs& A, int r) {
+  constexpr int s0 = PH & 3, s1 = (PH + 1) & 3, s2 = (PH + 2) & 3, s3 = (PH + 3) & 3;
+  S.rw[s3] = S.fs[(long long)S.yr * S.nx + S.xc];
+  if (++S.yr == S.ny) S.yr = 0;
+  S.ct[s2] = tri_dir<PY>(S.rw[s1], S.rw[s2], S.rw[s3]);
+  // upwind below: triples of rows y - 1, y, y + 1; above: y + 2, y + 1, y
+  const double fyr = PY ? face3(S.ct[s3].bp, S.ct[s3].qp, S.ct[s0].b0, S.ct[s0].q0, S.ct[s1].bm, S.ct[s1].qm, S.eps4)
+                        : face3(S.ct[s2].bp, S.ct[s2].qp, S.ct[s1].b0, S.ct[s1].q0, S.ct[s0].bm, S.ct[s0].qm, S.eps4);
+  const double c0 = S.rw[s0];
+  const double m1 = __shfl_up(c0, 1), p1 = __shfl_down(c0, 1);
+  const Tri tx = tri_dir<PX>(m1, c0, p1);
+  double fxl;  // face between columns x - 1 and x
+  if (PX) {    // upwind left: triples of columns x - 2, x - 1, x
+    fxl = face3(__shfl_up(tx.bp, 2), __shfl_up(tx.qp, 2), __shfl_up(tx.b0, 1), __shfl_up(tx.q0, 1), tx.bm, tx.qm,
+                S.eps4);
+  } else {     // upwind right: triples of columns x + 1, x, x - 1
+    fxl = face3(__shfl_down(tx.bp, 1), __shfl_down(tx.qp, 1), tx.b0, tx.q0, __shfl_up(tx.bm, 1), __shfl_up(tx.qm, 1),
+                S.eps4);
+  }
+  const double fxr = __shfl_down(fxl, 1);
+  const int y = S.y0 + r;
+  if (S.outcol && y < S.ny) {
+    const long long node = (long long)y * S.nx + S.xc;
+    const double adv = fma(S.pxi, fxl - fxr, S.pyi * (S.fyl - fyr));
+    const double f0v = A.first ? c0 : S.f0[node];
+    S.W[node] = fma(A.c, adv, fma(A.b, c0, A.a * f0v));
+  }
+  S.fyl = fyr;
+}
+
+template <bool PX, bool PY>
+__device__ __forceinline__ void adv_strip(AdvStrip& S, const AdvArgs& A) {
+  // rows y0 - 3 .. y0 + 2: triples of rows y0 - 2 .. y0 + 1, raw rows y0 .. y0 + 2
+  double p[6];
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    p[i] = S.fs[(long long)S.yr * S.nx + S.xc];
+    if (++S.yr == S.ny) S.yr = 0;
+  }
+  S.ct[2] = tri_dir<PY>(p[0], p[1], p[2]);  // row y0 - 2
+  S.ct[3] = tri_dir<PY>(p[1], p[2], p[3]);  // row y0 - 1
+  S.ct[0] = tri_dir<PY>(p[2], p[3], p[4]);  // row y0
+  S.ct[1] = tri_dir<PY>(p[3], p[4], p[5]);  // row y0 + 1
+  S.rw[0] = p[3];
+  S.rw[1] = p[4];
+  S.rw[2] = p[5];
+  // face between rows y0 - 1 and y0
+  S.fyl = PY ? face3(S.ct[2].bp, S.ct[2].qp, S.ct[3].b0, S.ct[3].q0, S.ct[0].bm, S.ct[0].qm, S.eps4)
+             : face3(S.ct[1].bp, S.ct[1].qp, S.ct[0].b0, S.ct[0].q0, S.ct[3].bm, S.ct[3].qm, S.eps4);
+  for (int r = 0; r < AR; r += 4) {
+    adv_row<PX, PY, 0>(S, A, r);
+    adv_row<PX, PY, 1>(S, A, r + 1);
+    adv_row<PX, PY, 2>(S, A, r + 2);
+    adv_row<PX, PY, 3>(S, A, r + 3);
+  }
 }
 
 __global__ __launch_bounds__(ANT) void adv_kernel(Dev D, AdvArgs A, const double* __restrict__ vel) {
@@ -326,7 +434,8 @@ __global__ __launch_bounds__(ANT) void adv_kernel(Dev D, AdvArgs A, const double
   unsigned b = blockIdx.x;
   const unsigned nb = gridDim.x;
   if ((nb & 7u) == 0) b = (b & 7u) * (nb >> 3) + (b >> 3);
-  const unsigned strip = b * 4u + (threadIdx.x >> 6);
+  const unsigned wave = (unsigned)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const unsigned strip = b * 4u + wave;
   const unsigned per_plane = (unsigned)nsx * (unsigned)nsy;
   const int plane = (int)(strip / per_plane);
   if (plane >= 2 * V) return;  // whole wavefront past the last strip
@@ -334,50 +443,28 @@ __global__ __launch_bounds__(ANT) void adv_kernel(Dev D, AdvArgs A, const double
   const int sy = (int)(sp / (unsigned)nsx), sx = (int)(sp - (unsigned)sy * (unsigned)nsx);
   const int v = plane % V, k = v / Q, l = v - k * Q;
   const double px = vel[k], py = vel[l];
-  const bool posx = px > 0.0, posy = py > 0.0;
   const long long base = (long long)plane * D.ntot;
-  const double* fs = A.fs + base;
   const int t = threadIdx.x & 63;
-  const int x0 = sx * AW, y0 = sy * AR;
-  const int xc = wrap(x0 - 3 + t, D.nx);
-  const bool outcol = t >= 3 && t < 3 + AW && x0 + t - 3 < D.nx;
-  const double eps = D.weno_eps;
-  // window rows y0 - 3 .. y0 + 2
-  double w[6];
-  int yr = wrap(y0 - 3, D.ny);
-#pragma unroll
-  for (int i = 0; i < 6; ++i) {
-    w[i] = fs[(long long)yr * D.nx + xc];
-    if (++yr == D.ny) yr = 0;
-  }
-  double fyl = face(w, posy, eps);  // face between rows y0 - 1 and y0
-  // yr is now row y0 + 3
-  for (int r = 0; r < AR; ++r) {
-    const int y = y0 + r;
-#pragma unroll
-    for (int i = 0; i < 5; ++i) w[i] = w[i + 1];
-    w[5] = fs[(long long)yr * D.nx + xc];  // row y + 3
-    if (++yr == D.ny) yr = 0;
-    const double fyr = face(w, posy, eps);  // face between rows y and y + 1
-    // row values of the neighbouring columns
-    const double c0 = w[2];
-    const double m1 = __shfl_up(c0, 1), m2 = __shfl_up(c0, 2), p1 = __shfl_down(c0, 1);
-    double fxl;
-    if (posx) {
-      const double m3 = __shfl_up(c0, 3);
-      fxl = weno5(m3, m2, m1, c0, p1, eps);   // face between columns x - 1 and x
-    } else {
-      const double p2 = __shfl_down(c0, 2);
-      fxl = weno5(p2, p1, c0, m1, m2, eps);
-    }
-    const double fxr = __shfl_down(fxl, 1);
-    if (outcol && y < D.ny) {
-      const long long node = (long long)y * D.nx + xc;
-      const double adv = -(px * (fxr - fxl) + py * (fyr - fyl)) * D.inv_dx;
-      const double f0v = A.first ? c0 : A.f0[base + node];
-      A.W[base + node] = A.a * f0v + A.b * c0 + A.c * adv;
-    }
-    fyl = fyr;
+  AdvStrip S;
+  S.fs = A.fs + base;
+  S.f0 = A.f0 + base;
+  S.W = A.W + base;
+  S.nx = D.nx;
+  S.ny = D.ny;
+  S.y0 = sy * AR;
+  const int x0 = sx * AW;
+  S.xc = wrap(x0 - 3 + t, D.nx);
+  S.yr = wrap(S.y0 - 3, D.ny);
+  S.outcol = t >= 3 && t < 3 + AW && x0 + t - 3 < D.nx;
+  S.pxi = px * D.inv_dx;
+  S.pyi = py * D.inv_dx;
+  S.eps4 = 4.0 * D.weno_eps;
+  if (px > 0.0) {
+    if (py > 0.0) adv_strip<true, true>(S, A);
+    else adv_strip<true, false>(S, A);
+  } else {
+    if (py > 0.0) adv_strip<false, true>(S, A);
+    else adv_strip<false, false>(S, A);
   }
 }
 
