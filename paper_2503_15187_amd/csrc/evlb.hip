@@ -128,6 +128,8 @@ struct Smem {
   };
   double nf[NFIELD][W];
   double tab[Shape<Q, W, NG>::UNIFORM ? 1 : 2 * Q * Q + Q];  // meq, dpm, vel
+  double sav[2 * MS_MAX + 1];      // averaging weights
+  double cf[MF_MAX];               // EV1 force taps
 };
 
 __device__ __forceinline__ int wrapi(int i, int n) {
@@ -136,16 +138,36 @@ __device__ __forceinline__ int wrapi(int i, int n) {
   return i;
 }
 
+// Constant tables into LDS: the averaging weights and force taps always, the
+// velocity tables for the narrow shapes.  All loads are issued before the
+// first LDS write, so the copy costs one memory round trip.
 template <int Q, int W, int NG>
 __device__ __forceinline__ void load_tables(const DevParams& P, Smem<Q, W, NG>& S) {
-  if constexpr (!Shape<Q, W, NG>::UNIFORM) {
-    for (int i = threadIdx.x; i < Q * Q; i += Shape<Q, W, NG>::NT) {
-      S.tab[i] = P.meq[i];
-      S.tab[Q * Q + i] = P.dpm[i];
-    }
-    for (int i = threadIdx.x; i < Q; i += Shape<Q, W, NG>::NT) S.tab[2 * Q * Q + i] = P.vel[i];
-    __syncthreads();
+  constexpr int NT = Shape<Q, W, NG>::NT;
+  constexpr int NTAB = Shape<Q, W, NG>::UNIFORM ? 0 : 2 * Q * Q + Q;
+  constexpr int NSAV = 2 * MS_MAX + 1;
+  constexpr int NALL = NTAB + NSAV + MF_MAX;
+  constexpr int L = (NALL + NT - 1) / NT;
+  const int tid = threadIdx.x;
+  double v[L];
+#pragma unroll
+  for (int i = 0; i < L; ++i) {
+    const int e = tid + i * NT;
+    v[i] = 0.0;
+    if (NTAB > 0 && e < Q * Q) v[i] = P.meq[e];
+    else if (NTAB > 0 && e < 2 * Q * Q) v[i] = P.dpm[e - Q * Q];
+    else if (e < NTAB) v[i] = P.vel[e - 2 * Q * Q];
+    else if (e < NTAB + 2 * P.ms + 1) v[i] = P.savg[e - NTAB];
+    else if (e >= NTAB + NSAV && e < NTAB + NSAV + P.mf) v[i] = P.cfor[e - NTAB - NSAV];
   }
+#pragma unroll
+  for (int i = 0; i < L; ++i) {
+    const int e = tid + i * NT;
+    if (e < NTAB) S.tab[e] = v[i];
+    else if (e < NTAB + NSAV) S.sav[e - NTAB] = v[i];
+    else if (e < NALL) S.cf[e - NTAB - NSAV] = v[i];
+  }
+  __syncthreads();
 }
 
 // One stage over one tile (see file header).
@@ -179,20 +201,58 @@ __device__ void stage_tile(const DevParams& P, const StageArgs& A, int tile, Sme
       Gn[v] = A.f_n[(long long)(Q + kbase + v) * ntot + gnode];
     }
   }
-  for (int idx = tid; idx < 2 * Q * (W + 2 * HF); idx += NT) {
-    const int r = idx / (W + 2 * HF);
-    const int c = idx - r * (W + 2 * HF);
-    S.f[r][c] = A.f_prev[(long long)r * ntot + off + wrapi(i0 - HF + c, nsys)];
+  // tile + WENO halo of F and G, the density window, u and T on the tile +-2:
+  // every load is issued before the first LDS write (one round trip)
+  constexpr int FW = W + 2 * HF;
+  constexpr int NFV = 2 * Q * FW;
+  constexpr int LF = (NFV + NT - 1) / NT;
+  double fv[LF];
+#pragma unroll
+  for (int i = 0; i < LF; ++i) {
+    const int idx = tid + i * NT;
+    fv[i] = 0.0;
+    if (idx < NFV) {
+      const int r = idx / FW;
+      const int c = idx - r * FW;
+      fv[i] = A.f_prev[(long long)r * ntot + off + wrapi(i0 - HF + c, nsys)];
+    }
   }
   const double* mn = A.mom_in;
-  for (int c = tid; c < W + 2 * hn; c += NT) S.n[c] = mn[off + wrapi(i0 - hn + c, nsys)];
-  for (int c = tid; c < W + 4; c += NT) {
-    const int node = off + wrapi(i0 - 2 + c, nsys);
-    S.u[c] = mn[ntot + node];
-    S.T[c] = mn[2 * ntot + node];
+  constexpr int LN = (W + 2 * HN_MAX + NT - 1) / NT;
+  const int nwin = W + 2 * hn;
+  double nv[LN];
+#pragma unroll
+  for (int i = 0; i < LN; ++i) {
+    const int c = tid + i * NT;
+    nv[i] = 0.0;
+    if (c < nwin) nv[i] = mn[off + wrapi(i0 - hn + c, nsys)];
+  }
+  static_assert(NT >= W + 4, "one thread per node of the tile +-2");
+  double uv = 0.0, Tv = 0.0;
+  if (tid < W + 4) {
+    const int node = off + wrapi(i0 - 2 + tid, nsys);
+    uv = mn[ntot + node];
+    Tv = mn[2 * ntot + node];
   }
   double qj = 0.0;
   if (tid >= W && tid < 2 * W) qj = mn[3 * ntot + off + wrapi(i0 + j, nsys)];
+#pragma unroll
+  for (int i = 0; i < LF; ++i) {
+    const int idx = tid + i * NT;
+    if (idx < NFV) {
+      const int r = idx / FW;
+      S.f[r][idx - r * FW] = fv[i];
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < LN; ++i) {
+    const int c = tid + i * NT;
+    if (c < nwin) S.n[c] = nv[i];
+  }
+  if (tid < W + 4) {
+    S.u[tid] = uv;
+    S.T[tid] = Tv;
+  }
   __syncthreads();
 
   // ---- 2. contact value, Hermite moments, force partial sums, WENO faces ---
@@ -203,10 +263,10 @@ __device__ void stage_tile(const DevParams& P, const StageArgs& A, int tile, Sme
       double s0 = 0.0, s1 = 0.0;
       int jj = -P.ms;
       for (; jj + 1 <= P.ms; jj += 2) {
-        s0 += P.savg[jj + P.ms] * S.n[cn + jj];
-        s1 += P.savg[jj + 1 + P.ms] * S.n[cn + jj + 1];
+        s0 += S.sav[jj + P.ms] * S.n[cn + jj];
+        s1 += S.sav[jj + 1 + P.ms] * S.n[cn + jj + 1];
       }
-      if (jj <= P.ms) s0 += P.savg[jj + P.ms] * S.n[cn + jj];
+      if (jj <= P.ms) s0 += S.sav[jj + P.ms] * S.n[cn + jj];
       const double eta = P.eta_c * (s0 + s1);
       const double om = 1.0 - eta;
       const double chi = (2.0 - eta) / (2.0 * om * om * om);
@@ -238,10 +298,10 @@ __device__ void stage_tile(const DevParams& P, const StageArgs& A, int tile, Sme
       double s0 = 0.0, s1 = 0.0;
       int m = m0;
       for (; m + 1 <= m1; m += 2) {
-        s0 += P.cfor[m - 1] * (S.n[cn + m] - S.n[cn - m]);
-        s1 += P.cfor[m] * (S.n[cn + m + 1] - S.n[cn - m - 1]);
+        s0 += S.cf[m - 1] * (S.n[cn + m] - S.n[cn - m]);
+        s1 += S.cf[m] * (S.n[cn + m + 1] - S.n[cn - m - 1]);
       }
-      if (m <= m1) s0 += P.cfor[m - 1] * (S.n[cn + m] - S.n[cn - m]);
+      if (m <= m1) s0 += S.cf[m - 1] * (S.n[cn + m] - S.n[cn - m]);
       S.fpart[g][j] = s0 + s1;
     }
     if (P.term_mask & EVLB_TERM_ADV) {
@@ -450,6 +510,8 @@ struct SmemCol {
   double f[2 * Q][WC + 2 * HF + 1];  // columns: node i0 - 3 + c, c = 0..68
   double n[WC + 2 * HN_MAX];
   double u[WC + 4], T[WC + 4], X[WC + 4], chi[WC + 4];
+  double sav[2 * MS_MAX + 1];        // averaging weights
+  double cf[MF_MAX];                 // EV1 force taps
 };
 
 template <int Q>
@@ -485,14 +547,58 @@ __device__ void stage_tile_col(const DevParams& P, const StageArgs& A, int tile,
       for (int r = 0; r < 2 * Q; ++r) S.f[r][c] = A.f_prev[(long long)r * ntot + gh];
     }
   }
+  // density window, u and T on nodes -2..64, the averaging and force tables:
+  // all loads issued before the first LDS write
   const double* mn = A.mom_in;
-  for (int c = lane; c < WC + 2 * hn; c += 64) S.n[c] = mn[off + wrapi(i0 - hn + c, nsys)];
-  for (int c = lane; c < WC + 4; c += 64) {
-    const int node = off + wrapi(i0 - 2 + c, nsys);
-    S.u[c] = mn[ntot + node];
-    S.T[c] = mn[2 * ntot + node];
+  constexpr int LN = (WC + 2 * HN_MAX + 63) / 64;
+  constexpr int LU = (WC + 4 + 63) / 64;
+  constexpr int NSAV = 2 * MS_MAX + 1;
+  constexpr int LT = (NSAV + MF_MAX + 63) / 64;
+  const int nwin = WC + 2 * hn;
+  double nv[LN], uv[LU], Tv[LU], tv[LT];
+#pragma unroll
+  for (int i = 0; i < LN; ++i) {
+    const int c = lane + 64 * i;
+    nv[i] = c < nwin ? mn[off + wrapi(i0 - hn + c, nsys)] : 0.0;
+  }
+#pragma unroll
+  for (int i = 0; i < LU; ++i) {
+    const int c = lane + 64 * i;
+    uv[i] = 0.0;
+    Tv[i] = 0.0;
+    if (c < WC + 4) {
+      const int node = off + wrapi(i0 - 2 + c, nsys);
+      uv[i] = mn[ntot + node];
+      Tv[i] = mn[2 * ntot + node];
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < LT; ++i) {
+    const int e = lane + 64 * i;
+    tv[i] = 0.0;
+    if (e < 2 * P.ms + 1) tv[i] = P.savg[e];
+    else if (e >= NSAV && e < NSAV + P.mf) tv[i] = P.cfor[e - NSAV];
   }
   const double qj = valid ? mn[3 * ntot + gnode] : 0.0;
+#pragma unroll
+  for (int i = 0; i < LN; ++i) {
+    const int c = lane + 64 * i;
+    if (c < nwin) S.n[c] = nv[i];
+  }
+#pragma unroll
+  for (int i = 0; i < LU; ++i) {
+    const int c = lane + 64 * i;
+    if (c < WC + 4) {
+      S.u[c] = uv[i];
+      S.T[c] = Tv[i];
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < LT; ++i) {
+    const int e = lane + 64 * i;
+    if (e < NSAV) S.sav[e] = tv[i];
+    else if (e < NSAV + MF_MAX) S.cf[e - NSAV] = tv[i];
+  }
   __syncthreads();
 
   // ---- 2. contact value and X = n^2 chi T on nodes -2..64 ---------------
@@ -501,10 +607,10 @@ __device__ void stage_tile_col(const DevParams& P, const StageArgs& A, int tile,
     double s0 = 0.0, s1 = 0.0;
     int jj = -P.ms;
     for (; jj + 1 <= P.ms; jj += 2) {
-      s0 += P.savg[jj + P.ms] * S.n[cn + jj];
-      s1 += P.savg[jj + 1 + P.ms] * S.n[cn + jj + 1];
+      s0 += S.sav[jj + P.ms] * S.n[cn + jj];
+      s1 += S.sav[jj + 1 + P.ms] * S.n[cn + jj + 1];
     }
-    if (jj <= P.ms) s0 += P.savg[jj + P.ms] * S.n[cn + jj];
+    if (jj <= P.ms) s0 += S.sav[jj + P.ms] * S.n[cn + jj];
     const double eta = P.eta_c * (s0 + s1);
     const double om = 1.0 - eta;
     const double chi = (2.0 - eta) / (2.0 * om * om * om);
@@ -524,12 +630,12 @@ __device__ void stage_tile_col(const DevParams& P, const StageArgs& A, int tile,
     double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
     int m = 1;
     for (; m + 3 <= P.mf; m += 4) {
-      s0 += P.cfor[m - 1] * (S.n[cn + m] - S.n[cn - m]);
-      s1 += P.cfor[m] * (S.n[cn + m + 1] - S.n[cn - m - 1]);
-      s2 += P.cfor[m + 1] * (S.n[cn + m + 2] - S.n[cn - m - 2]);
-      s3 += P.cfor[m + 2] * (S.n[cn + m + 3] - S.n[cn - m - 3]);
+      s0 += S.cf[m - 1] * (S.n[cn + m] - S.n[cn - m]);
+      s1 += S.cf[m] * (S.n[cn + m + 1] - S.n[cn - m - 1]);
+      s2 += S.cf[m + 1] * (S.n[cn + m + 2] - S.n[cn - m - 2]);
+      s3 += S.cf[m + 2] * (S.n[cn + m + 3] - S.n[cn - m - 3]);
     }
-    for (; m <= P.mf; ++m) s0 += P.cfor[m - 1] * (S.n[cn + m] - S.n[cn - m]);
+    for (; m <= P.mf; ++m) s0 += S.cf[m - 1] * (S.n[cn + m] - S.n[cn - m]);
     Fx += (s0 + s1) + (s2 + s3);
   } else if (P.force_model == EVLB_FORCE_EV2) {
     const double d1 = (S.n[cn - 2] - 8.0 * S.n[cn - 1] + 8.0 * S.n[cn + 1] - S.n[cn + 2]) * idx12;
