@@ -17,6 +17,12 @@
 //               next stage.
 // Global state is structure-of-arrays [2][q][n_tot] (node fastest), so every
 // row load and store of a wavefront is one contiguous 512-byte segment.
+//
+// Tile shapes: wide tiles (64 nodes, groups of velocities per wavefront,
+// tables through the scalar cache), narrow tiles (16 nodes, one update per
+// thread, the velocity-space contractions on the f64 MFMA) for grids too
+// small to fill the chip, and column tiles (one wavefront of 63 nodes, a
+// node's whole velocity column in registers) for large grids.
 
 #include <hip/hip_runtime.h>
 
@@ -24,6 +30,7 @@
 #include <cstdint>
 #include <cstring>
 #include <new>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/evlb.h"
@@ -52,6 +59,7 @@ struct DevParams {
   const double* ssig;  // [2 ms + 1] d savg / d sigma
   const int4* tiles;   // {system offset, system nodes, tile start, 0}
   int ntiles;
+  int single;          // one system: tile t starts at node t * width
   int ms, mf, hn;
   long long ntot;
   double dx, inv_dx, dt;
@@ -101,7 +109,8 @@ __device__ __forceinline__ double weno5(double v0, double v1, double v2, double 
 // Launch shape of the stage kernel: tiles of W nodes, NG groups of
 // velocities (thread = node j x group g, NT = W * NG threads).  With W = 64
 // a velocity group is uniform over a wavefront and the constant tables are
-// read through the scalar cache; narrower tiles keep them in LDS.
+// read through the scalar cache; narrower tiles keep them in LDS (the
+// 16-node shape has its own tile function, stage_tile_narrow).
 template <int Q, int W, int NG>
 struct Shape {
   static constexpr int NT = W * NG;
@@ -153,12 +162,16 @@ __device__ __forceinline__ void load_tables(const DevParams& P, Smem<Q, W, NG>& 
 #pragma unroll
   for (int i = 0; i < L; ++i) {
     const int e = tid + i * NT;
-    v[i] = 0.0;
-    if (NTAB > 0 && e < Q * Q) v[i] = P.meq[e];
-    else if (NTAB > 0 && e < 2 * Q * Q) v[i] = P.dpm[e - Q * Q];
-    else if (e < NTAB) v[i] = P.vel[e - 2 * Q * Q];
-    else if (e < NTAB + 2 * P.ms + 1) v[i] = P.savg[e - NTAB];
-    else if (e >= NTAB + NSAV && e < NTAB + NSAV + P.mf) v[i] = P.cfor[e - NTAB - NSAV];
+    // one load per entry through a selected pointer (separate loads in the
+    // branches would be serialised by the register they share)
+    const double* src = nullptr;
+    int si = 0;
+    if (NTAB > 0 && e < Q * Q) { src = P.meq; si = e; }
+    else if (NTAB > 0 && e < 2 * Q * Q) { src = P.dpm; si = e - Q * Q; }
+    else if (e < NTAB) { src = P.vel; si = e - 2 * Q * Q; }
+    else if (e < NTAB + 2 * P.ms + 1) { src = P.savg; si = e - NTAB; }
+    else if (e >= NTAB + NSAV && e < NTAB + NSAV + P.mf) { src = P.cfor; si = e - NTAB - NSAV; }
+    v[i] = src ? src[si] : 0.0;
   }
 #pragma unroll
   for (int i = 0; i < L; ++i) {
@@ -488,11 +501,416 @@ __device__ void stage_tile(const DevParams& P, const StageArgs& A, int tile, Sme
   __syncthreads();
 }
 
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+// ---------------------------------------------------------------------------
+// Narrow shape: WN = 16 nodes x Q velocities, one update per thread
+// (tid = k * 16 + j), Q / 4 wavefronts.  Built for grids too small to fill
+// the chip, where a stage is a chain of latencies: every global load of a
+// tile goes out in one batch, and the velocity-space contractions
+//   E_k = sum_l meq[k][l] a_l,  (Dp F)_k = sum_k' dpm[k][k'] F_k'  (and G)
+// run on v_mfma_f64_16x16x4 as (Q x Q) x (Q x 16 nodes) products (A operand
+// [i][c] from lane i + 16 c, B operand [c][col] from lane col + 16 c, result
+// [4 r + c][col] in register r of lane col + 16 c), so an update reads three
+// LDS values instead of 3 Q.  The Dp chains need only the tile and run with
+// the contact values and faces; the equilibrium chains wait for the Hermite
+// moments and run with the node fields, on wavefronts other than the one
+// that computes the fields.
+// ---------------------------------------------------------------------------
+constexpr int WN = 16;
+
+template <int Q>
+struct SmemN {
+  double f[2 * Q][WN + 2 * HF];  // F rows then G rows, tile + WENO halo
+  double flux[2 * Q][WN + 1];    // WENO-5 face values
+  double n[WN + 2 * HN_MAX];     // density window
+  double u[WN + 4], T[WN + 4], X[WN + 4], chi[WN + 4];
+  double a[Q][WN];               // Hermite moments of the local Maxwellian
+  double fpart[Q][WN];           // EV1 partial force sums
+  double ctr[3][Q][WN];          // E, Dp F, Dp G
+  double nf[NFIELD][WN];
+  double red[Q / 4][6][WN];      // per-wavefront velocity moments
+  double sav[2 * MS_MAX + 1];
+  double cf[MF_MAX];
+};
+
+template <int Q>
+__device__ void stage_tile_narrow(const DevParams& P, const StageArgs& A, int tile, SmemN<Q>& S) {
+  constexpr int W = WN, NT = W * Q, NW = Q / 4;
+  constexpr int RB = (Q + 15) / 16;  // row blocks of 16 output rows
+  constexpr int KC = Q / 4;          // contraction steps of 4
+  static_assert(2 * RB <= NW, "one Dp chain per wavefront");
+  static_assert(NT >= 2 * MS_MAX + 1 + MF_MAX, "one thread per table entry");
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int j = tid % W, k = tid / W;
+  int off, nsys, i0;
+  if (P.single) {
+    off = 0;
+    nsys = (int)P.ntot;
+    i0 = tile * W;
+  } else {
+    const int4 td = P.tiles[tile];
+    off = td.x;
+    nsys = td.y;
+    i0 = td.z;
+  }
+  const long long ntot = P.ntot;
+  const int hn = P.hn;
+  const bool valid = (i0 + j) < nsys;
+  const long long gnode = off + i0 + j;
+
+  // MFMA chains of this wavefront: Dp chain i < 2 RB (F then G, row block
+  // i mod RB) and equilibrium chain rb < RB run on wavefront (1 + i) mod NW
+  // and (1 + rb) mod NW (wavefront 0 computes the node fields)
+  int chD = -1, chE = -1;
+#pragma unroll
+  for (int i = 0; i < 2 * RB; ++i)
+    if ((1 + i) % NW == wave) chD = i;
+#pragma unroll
+  for (int rb = 0; rb < RB; ++rb)
+    if ((1 + rb) % NW == wave) chE = rb;
+  const bool dchain = chD >= 0 && (P.term_mask & EVLB_TERM_FORCE);
+
+  // ---- 1. load: one batch of global loads, then the LDS writes ----------
+  double aD[KC], aE[KC];  // MFMA A operands: table rows 16 rb + (lane & 15)
+  {
+    const int rowD = 16 * (chD % RB) + (lane & 15), rowE = 16 * chE + (lane & 15);
+#pragma unroll
+    for (int b = 0; b < KC; ++b) {
+      const int col = 4 * b + (lane >> 4);
+      aD[b] = dchain && rowD < Q ? P.dpm[rowD * Q + col] : 0.0;
+      aE[b] = chE >= 0 && rowE < Q ? P.meq[rowE * Q + col] : 0.0;
+    }
+  }
+  const double pk = P.vel[k];
+  double Fn = 0.0, Gn = 0.0;
+  if (!A.first && !A.rhs_mode && valid) {
+    Fn = A.f_n[(long long)k * ntot + gnode];
+    Gn = A.f_n[(long long)(Q + k) * ntot + gnode];
+  }
+  constexpr int FW = W + 2 * HF;
+  constexpr int NFV = 2 * Q * FW;
+  constexpr int LF = (NFV + NT - 1) / NT;
+  double fv[LF];
+#pragma unroll
+  for (int i = 0; i < LF; ++i) {
+    const int idx = tid + i * NT;
+    fv[i] = 0.0;
+    if (idx < NFV) {
+      const int r = idx / FW;
+      fv[i] = A.f_prev[(long long)r * ntot + off + wrapi(i0 - HF + idx - r * FW, nsys)];
+    }
+  }
+  const double* mn = A.mom_in;
+  constexpr int LN = (W + 2 * HN_MAX + NT - 1) / NT;
+  const int nwin = W + 2 * hn;
+  double nv[LN];
+#pragma unroll
+  for (int i = 0; i < LN; ++i) {
+    const int c = tid + i * NT;
+    nv[i] = c < nwin ? mn[off + wrapi(i0 - hn + c, nsys)] : 0.0;
+  }
+  // thread c < W + 4 owns node i0 - 2 + c: u, T, q
+  double uv = 0.0, Tv = 0.0, qv = 0.0;
+  if (tid < W + 4) {
+    const int node = off + wrapi(i0 - 2 + tid, nsys);
+    uv = mn[ntot + node];
+    Tv = mn[2 * ntot + node];
+    qv = mn[3 * ntot + node];
+  }
+  // averaging weights and force taps: threads NT - 97 .. NT - 1
+  constexpr int NSAV = 2 * MS_MAX + 1;
+  const int e = tid - (NT - NSAV - MF_MAX);
+  const double* src = nullptr;
+  int si = 0;
+  if (e >= 0 && e < 2 * P.ms + 1) { src = P.savg; si = e; }
+  else if (e >= NSAV && e < NSAV + P.mf) { src = P.cfor; si = e - NSAV; }
+  const double tv = src ? src[si] : 0.0;
+#pragma unroll
+  for (int i = 0; i < LF; ++i) {
+    const int idx = tid + i * NT;
+    if (idx < NFV) {
+      const int r = idx / FW;
+      S.f[r][idx - r * FW] = fv[i];
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < LN; ++i) {
+    const int c = tid + i * NT;
+    if (c < nwin) S.n[c] = nv[i];
+  }
+  if (tid < W + 4) {
+    S.u[tid] = uv;
+    S.T[tid] = Tv;
+  }
+  if (e >= 0 && e < NSAV) S.sav[e] = tv;
+  else if (e >= NSAV) S.cf[e - NSAV] = tv;
+  __syncthreads();
+
+  // ---- 2. contact value, transport, Hermite moments, force sums, faces ----
+  if (tid < W + 4) {
+    // chi(nbar) and X = n^2 chi T on the tile +-2 (eq:carnstar)
+    const int c = tid, cn = c + hn - 2;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    int jj = -P.ms;
+    for (; jj + 3 <= P.ms; jj += 4) {
+      s0 += S.sav[jj + P.ms] * S.n[cn + jj];
+      s1 += S.sav[jj + 1 + P.ms] * S.n[cn + jj + 1];
+      s2 += S.sav[jj + 2 + P.ms] * S.n[cn + jj + 2];
+      s3 += S.sav[jj + 3 + P.ms] * S.n[cn + jj + 3];
+    }
+    for (; jj <= P.ms; ++jj) s0 += S.sav[jj + P.ms] * S.n[cn + jj];
+    const double eta = P.eta_c * ((s0 + s1) + (s2 + s3));
+    const double om = 1.0 - eta;
+    const double chi = (2.0 - eta) / (2.0 * om * om * om);
+    const double nn = S.n[cn];
+    S.chi[c] = chi;
+    S.X[c] = nn * nn * chi * Tv;
+    if (c >= 2 && c < W + 2) {
+      // transport of the own node: mu (eq:viscosity), tau (eq:tau), Pr (eq:prandtl)
+      const double bn = P.b * nn;
+      const double y = bn * chi;
+      const double mu0 = P.mu0c * sqrt(Tv);
+      const double c12 = 0.16 * (1.0 + 12.0 / M_PI);
+      const double c32 = 0.36 * (1.0 + 32.0 / (9.0 * M_PI));
+      const double mu = mu0 * (1.0 / chi + 0.8 * bn + c12 * bn * bn * chi);
+      S.nf[NF_NU][c - 2] = chi * nn * Tv * (1.0 + 0.4 * y) / mu;
+      const double Pr = (2.0 / 3.0) * (1.0 + 0.6 * y) * (1.0 + 0.8 * y + c12 * y * y) /
+                        ((1.0 + 0.4 * y) * (1.0 + 1.2 * y + c32 * y * y));
+      S.nf[NF_S][c - 2] = (1.0 - Pr) * qv / (5.0 * nn * Tv * Tv);
+      S.nf[NF_PRE][c - 2] = -bn * chi;
+    }
+  }
+  if (tid >= NT - W) {
+    // Hermite moments a_0 = n, a_1 = n u, a_{l+1} = u a_l + l (T - 1) a_{l-1}
+    const int jn = tid - (NT - W);
+    const double n = S.n[jn + hn], u = S.u[jn + 2], tm1 = S.T[jn + 2] - 1.0;
+    double am = n, a = n * u;
+    S.a[0][jn] = am;
+    S.a[1][jn] = a;
+#pragma unroll
+    for (int l = 1; l < Q - 1; ++l) {
+      const double an = u * a + (double)l * tm1 * am;
+      am = a;
+      a = an;
+      S.a[l + 1][jn] = a;
+    }
+  }
+  if (P.force_model == EVLB_FORCE_EV1) {
+    // node j, chunk k of the paired taps
+    const int ch = (P.mf + Q - 1) / Q;
+    const int m0 = 1 + k * ch;
+    const int m1 = min(P.mf, m0 + ch - 1);
+    const int cn = j + hn;
+    double s0 = 0.0, s1 = 0.0;
+    int m = m0;
+    for (; m + 1 <= m1; m += 2) {
+      s0 += S.cf[m - 1] * (S.n[cn + m] - S.n[cn - m]);
+      s1 += S.cf[m] * (S.n[cn + m + 1] - S.n[cn - m - 1]);
+    }
+    if (m <= m1) s0 += S.cf[m - 1] * (S.n[cn + m] - S.n[cn - m]);
+    S.fpart[k][j] = s0 + s1;
+  }
+  if ((P.term_mask & EVLB_TERM_ADV) && tid >= W + 4 && tid < NT - W) {
+    // faces on the threads without contact-value or Hermite work
+    constexpr int NFACE = 2 * Q * (W + 1);
+    constexpr int NFT = NT - 2 * W - 4;
+#pragma unroll
+    for (int i = 0; i < (NFACE + NFT - 1) / NFT; ++i) {
+      const int idx = tid - (W + 4) + i * NFT;
+      if (idx < NFACE) {
+        const int r = idx / (W + 1);
+        const int jf = idx - r * (W + 1);  // face i0 + jf - 1/2
+        const int kr = r < Q ? r : r - Q;
+        const bool pos = kr >= Q / 2;      // p_k > 0: upwind from the left
+        const double* fr = &S.f[r][0];
+        const int b0 = pos ? jf : jf + 5;
+        const int st = pos ? 1 : -1;
+        S.flux[r][jf] = weno5(fr[b0], fr[b0 + st], fr[b0 + 2 * st], fr[b0 + 3 * st], fr[b0 + 4 * st],
+                              P.weno_eps);
+      }
+    }
+  }
+  if (dchain) {
+    // (Dp F) or (Dp G) for one row block on the MFMA
+    const int p = 1 + chD / RB, rb = chD % RB;
+    const int col = lane & 15, c = lane >> 4;
+    const int brow = p == 2 ? Q : 0;
+    dbl4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int b = 0; b < KC; ++b)
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(aD[b], S.f[brow + 4 * b + c][col + HF], acc, 0, 0, 0);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = 16 * rb + 4 * r + c;
+      if (row < Q) S.ctr[p][row][col] = acc[r];
+    }
+  }
+  __syncthreads();
+
+  // ---- 3. force and gradients (threads < 16); equilibrium (MFMA) ----------
+  if (tid < W) {
+    const int c = j + 2, cn = j + hn;
+    const double idx12 = P.inv_dx * (1.0 / 12.0);
+    double Fx = P.g_ext;
+    if (P.force_model == EVLB_FORCE_EV1) {
+      double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+      for (int g = 0; g + 1 < Q; g += 2) {
+        s0 += S.fpart[g][j];
+        s1 += S.fpart[g + 1][j];
+      }
+      Fx += s0 + s1;
+    } else if (P.force_model == EVLB_FORCE_EV2) {
+      const double d1 = (S.n[cn - 2] - 8.0 * S.n[cn - 1] + 8.0 * S.n[cn + 1] - S.n[cn + 2]) * idx12;
+      const double d3 = (-S.n[cn - 2] + 2.0 * S.n[cn - 1] - 2.0 * S.n[cn + 1] + S.n[cn + 2]) *
+                        (0.5 * P.inv_dx * P.inv_dx * P.inv_dx);
+      Fx += P.two_a * d1 + P.kappa * d3;
+    }
+    const double T = S.T[c];
+    S.nf[NF_A][j] = (S.X[c - 2] - 8.0 * S.X[c - 1] + 8.0 * S.X[c + 1] - S.X[c + 2]) * idx12 / S.X[c];
+    S.nf[NF_B][j] = (S.T[c - 2] - 8.0 * S.T[c - 1] + 8.0 * S.T[c + 1] - S.T[c + 2]) * idx12 / T;
+    S.nf[NF_U1][j] = (S.u[c - 2] - 8.0 * S.u[c - 1] + 8.0 * S.u[c + 1] - S.u[c + 2]) * idx12;
+    S.nf[NF_FX][j] = Fx;
+    S.nf[NF_N][j] = S.n[cn];
+    S.nf[NF_U][j] = S.u[c];
+    S.nf[NF_T][j] = T;
+  }
+  if (chE >= 0) {
+    const int col = lane & 15, c = lane >> 4;
+    dbl4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int b = 0; b < KC; ++b)
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(aE[b], S.a[4 * b + c][col], acc, 0, 0, 0);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = 16 * chE + 4 * r + c;
+      if (row < Q) S.ctr[0][row][col] = acc[r];
+    }
+  }
+  __syncthreads();
+
+  // ---- 4. update -----------------------------------------------------------
+  double pm[6];
+  {
+    const double u = S.nf[NF_U][j], T = S.nf[NF_T][j];
+    const double nu = S.nf[NF_NU][j], sS = S.nf[NF_S][j], pre = S.nf[NF_PRE][j];
+    const double Ag = S.nf[NF_A][j], Bg = S.nf[NF_B][j], Ug = S.nf[NF_U1][j];
+    const double Fx = S.nf[NF_FX][j];
+    const double invT = 1.0 / T;
+    const double E = S.ctr[0][k][j];
+    const double F = S.f[k][j + HF];
+    const double G = S.f[Q + k][j + HF];
+    const double xi = pk - u;
+    const double th = xi * xi * invT;
+    double LF = 0.0, LG = 0.0;
+    if (P.term_mask & EVLB_TERM_ADV) {
+      LF = -pk * (S.flux[k][j + 1] - S.flux[k][j]) * P.inv_dx;
+      LG = -pk * (S.flux[Q + k][j + 1] - S.flux[Q + k][j]) * P.inv_dx;
+    }
+    if (P.term_mask & EVLB_TERM_FORCE) {
+      LF -= Fx * S.ctr[1][k][j];
+      LG -= Fx * S.ctr[2][k][j];
+    }
+    if (P.term_mask & EVLB_TERM_J0) {
+      const double FS = E * (1.0 + sS * xi * (th - 3.0));
+      const double GS = T * E * (1.0 + sS * xi * (th - 1.0));
+      LF -= nu * (F - FS);
+      LG -= nu * (G - GS);
+    }
+    if (P.term_mask & EVLB_TERM_J1) {
+      LF += pre * E * (xi * (Ag + 0.3 * (th - 3.0) * Bg) + 0.6 * (th - 1.0) * Ug);
+      LG += pre * T * E * (xi * (Ag + 0.3 * (th - 1.0) * Bg) + 0.2 * (3.0 * th - 1.0) * Ug);
+    }
+    double Fo, Go;
+    if (A.rhs_mode) {
+      Fo = LF;
+      Go = LG;
+    } else {
+      const double Fb = A.first ? F : Fn;
+      const double Gb = A.first ? G : Gn;
+      Fo = A.alpha * Fb + A.beta * (F + P.dt * LF);
+      Go = A.alpha * Gb + A.beta * (G + P.dt * LG);
+    }
+    if (valid) {
+      A.f_out[(long long)k * ntot + gnode] = Fo;
+      A.f_out[(long long)(Q + k) * ntot + gnode] = Go;
+    }
+    const double p2 = pk * pk;
+    pm[0] = Fo;
+    pm[1] = pk * Fo;
+    pm[2] = p2 * Fo;
+    pm[3] = p2 * pk * Fo;
+    pm[4] = Go;
+    pm[5] = pk * Go;
+  }
+  if (A.rhs_mode) {
+    __syncthreads();  // LDS is reused by the next tile
+    return;
+  }
+  // the four velocities of a node within a wavefront: lanes j, j + 16, j + 32, j + 48
+#pragma unroll
+  for (int m = 0; m < 6; ++m) {
+    pm[m] += __shfl_xor(pm[m], 16);
+    pm[m] += __shfl_xor(pm[m], 32);
+  }
+  if (lane < W) {
+#pragma unroll
+    for (int m = 0; m < 6; ++m) S.red[wave][m][j] = pm[m];
+  }
+  __syncthreads();
+
+  // ---- 5. moments of the new state --------------------------------------
+  if (tid < W && valid) {
+    double ms[6];
+#pragma unroll
+    for (int m = 0; m < 6; ++m) {
+      double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+      for (int w = 0; w + 1 < NW; w += 2) {
+        s0 += S.red[w][m][tid];
+        s1 += S.red[w + 1][m][tid];
+      }
+      if (NW & 1) s0 += S.red[NW - 1][m][tid];
+      ms[m] = s0 + s1;
+    }
+    const double n = ms[0];
+    const double u = ms[1] / n;
+    const double T = (2.0 / 3.0) * (0.5 * ms[2] + ms[4] - 0.5 * n * u * u) / n;
+    const double x3 = ms[3] - 3.0 * u * ms[2] + 3.0 * u * u * ms[1] - u * u * u * n;
+    const double q = 0.5 * x3 + ms[5] - u * ms[4];
+    A.mom_out[gnode] = n;
+    A.mom_out[ntot + gnode] = u;
+    A.mom_out[2 * ntot + gnode] = P.T_iso > 0.0 ? P.T_iso : T;
+    A.mom_out[3 * ntot + gnode] = q;
+    if (!(n > 0.0) || !(T > 0.0) || !isfinite(n) || !isfinite(T) || !isfinite(q) || !isfinite(u))
+      P.status[0] = 1;
+  }
+  __syncthreads();
+}
+
 template <int Q, int W, int NG>
 __global__ __launch_bounds__(W * NG) void stage_kernel(DevParams P, StageArgs A) {
-  __shared__ Smem<Q, W, NG> S;
-  load_tables<Q, W, NG>(P, S);
-  for (int t = blockIdx.x; t < P.ntiles; t += gridDim.x) stage_tile<Q, W, NG>(P, A, t, S);
+  if constexpr (W == WN) {
+    static_assert(NG == Q, "narrow tiles take one velocity per thread");
+    __shared__ SmemN<Q> S;
+    // every kernel argument into SGPRs before the first branch: one scalar
+    // round trip at entry instead of one at each first use
+    asm volatile("" ::"s"(P.meq), "s"(P.dpm), "s"(P.vel), "s"(P.savg), "s"(P.cfor), "s"(P.tiles), "s"(P.status),
+                 "s"(P.ntiles), "s"(P.single), "s"(P.ms), "s"(P.mf), "s"(P.hn), "s"(P.ntot), "s"(P.force_model),
+                 "s"(P.term_mask));
+    asm volatile("" ::"s"(P.inv_dx), "s"(P.dt), "s"(P.b), "s"(P.eta_c), "s"(P.mu0c), "s"(P.weno_eps), "s"(P.g_ext),
+                 "s"(P.two_a), "s"(P.kappa), "s"(P.T_iso));
+    asm volatile("" ::"s"(A.f_prev), "s"(A.f_n), "s"(A.f_out), "s"(A.mom_in), "s"(A.mom_out), "s"(A.alpha),
+                 "s"(A.beta), "s"(A.first), "s"(A.rhs_mode));
+    for (int t = blockIdx.x; t < P.ntiles; t += gridDim.x) stage_tile_narrow<Q>(P, A, t, S);
+  } else {
+    __shared__ Smem<Q, W, NG> S;
+    load_tables<Q, W, NG>(P, S);
+    for (int t = blockIdx.x; t < P.ntiles; t += gridDim.x) stage_tile<Q, W, NG>(P, A, t, S);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -575,9 +993,11 @@ __device__ void stage_tile_col(const DevParams& P, const StageArgs& A, int tile,
 #pragma unroll
   for (int i = 0; i < LT; ++i) {
     const int e = lane + 64 * i;
-    tv[i] = 0.0;
-    if (e < 2 * P.ms + 1) tv[i] = P.savg[e];
-    else if (e >= NSAV && e < NSAV + P.mf) tv[i] = P.cfor[e - NSAV];
+    const double* src = nullptr;
+    int si = 0;
+    if (e < 2 * P.ms + 1) { src = P.savg; si = e; }
+    else if (e >= NSAV && e < NSAV + P.mf) { src = P.cfor; si = e - NSAV; }
+    tv[i] = src ? src[si] : 0.0;
   }
   const double qj = valid ? mn[3 * ntot + gnode] : 0.0;
 #pragma unroll
@@ -836,11 +1256,14 @@ struct PersistArgs {
 template <int Q, int W, int NG>
 struct GroupShape {
   static constexpr int NT = W * NG;
-  typedef Smem<Q, W, NG> Shared;
-  __device__ static void prologue(const DevParams& P, Shared& S) { load_tables<Q, W, NG>(P, S); }
+  typedef std::conditional_t<W == WN, SmemN<Q>, Smem<Q, W, NG>> Shared;
+  __device__ static void prologue(const DevParams& P, Shared& S) {
+    if constexpr (W != WN) load_tables<Q, W, NG>(P, S);
+  }
   __device__ static void tile(const DevParams& P, const StageArgs& A, int t, Shared& S, const double*,
                               const double*, const double*) {
-    stage_tile<Q, W, NG>(P, A, t, S);
+    if constexpr (W == WN) stage_tile_narrow<Q>(P, A, t, S);
+    else stage_tile<Q, W, NG>(P, A, t, S);
   }
 };
 
@@ -954,7 +1377,7 @@ __global__ __launch_bounds__(256) void equilibrium_kernel(DevParams P, const dou
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 constexpr int WIDE = 64;    // tile width for large grids
-constexpr int NARROW = 16;  // tile width for grids too small to fill the chip
+constexpr int NARROW = WN;  // tile width for grids too small to fill the chip
 
 struct Layout {
   size_t tables, tiles_wide, tiles_narrow, tiles_col, tiles_adj, f1, f2, momA, momB, status;
@@ -1521,6 +1944,7 @@ int evlb_init(const evlb_params* params, void* d_workspace, size_t ws_bytes, voi
   d.ssig = d.csig + nc;
   d.tiles = (const int4*)(c->ws + L.tiles_wide);
   d.ntiles = L.ntiles_wide;
+  d.single = params->n_sys == 1;
   d.ms = L.ms;
   d.mf = L.mf;
   d.hn = L.mf > L.ms + 2 ? L.mf : L.ms + 2;

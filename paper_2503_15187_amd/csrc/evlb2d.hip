@@ -528,8 +528,12 @@ struct VelArgs {
 //   C = 0.2 pre div u,  pre = -b n chi.
 // For a fixed row (xx) P is a cubic in xy: alpha + xy (beta + xy (gamma +
 // delta xy)), set up once per row and pass.
+//
+// Occupancy: the unconstrained allocation takes about 300 registers (one
+// wavefront per SIMD); capped at 256 a few values spill to scratch, and the
+// second wavefront per SIMD hides more memory latency than the spills cost.
 template <bool FRC>
-__global__ __launch_bounds__(256) void vel_kernel(Dev D, VelArgs A, const double* __restrict__ vel,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void vel_kernel(Dev D, VelArgs A, const double* __restrict__ vel,
                                                   const double* __restrict__ meq,
                                                   const double* __restrict__ dpm) {
   __shared__ double s_ey[4][16][Q];  // per wave: e_l(u_y) of its 16 nodes
