@@ -1480,7 +1480,8 @@ Layout make_layout(const evlb_params* p) {
     L.adj_fa = off; off += align256(sizeof(double) * NFA * (size_t)L.ntot);
     L.adj_fb = off; off += align256(sizeof(double) * NFB * (size_t)L.ntot);
     L.adj_mom = off; off += mbytes;
-    L.adj_part = off; off += align256(sizeof(double) * 2 * 6 * (size_t)L.ntiles_adj);
+    // parameter partials: per VJP one slot per field-adjoint tile (16 nodes) and per node tile
+    L.adj_part = off; off += align256(sizeof(double) * 2 * 3 * (size_t)(L.ntiles_narrow + L.ntiles_adj));
     L.adj_lam = off; off += fbytes;
   }
   L.total = off;
@@ -1674,7 +1675,8 @@ DevParams params_adj(const evlb_ctx* c) {
 
 // g = (dL/df)^T v at state f (moments mom), written as
 // out = cc (v + dt g) + a1 X1 + a2 X2; parameter partials weighted by pw into
-// slots [2 * vjp_index, 2 * vjp_index + 1] of the partial buffer.
+// the slot range vjp_index of the partial buffer (one slot per field-adjoint
+// tile, then one per node tile).
 template <int Q>
 int launch_vjp(evlb_ctx* c, const double* f, const double* mom, const double* v, double* out, const double* X1,
                const double* X2, double cc, double a1, double a2, double pw, int vjp_index, hipStream_t st,
@@ -1701,12 +1703,15 @@ int launch_vjp(evlb_ctx* c, const double* f, const double* mom, const double* v,
   A.j = j;
   double* part = (double*)(c->ws + c->L.adj_part);
   const int nta = P.ntiles;
-  A.part = part + (size_t)(2 * vjp_index) * 2 * nta;
-  hipLaunchKernelGGL((adj_fields_kernel<Q>), dim3(nta), dim3(64 * NWA), 0, st, P, A, P.vel, P.meq, P.dpm);
+  const DevParams Pn = params_for(c, NARROW);
+  const int ntn = Pn.ntiles;
+  // slots of VJP i: ntn field-adjoint tiles, then nta node tiles
+  A.part = part + (size_t)vjp_index * 2 * (ntn + nta);
+  hipLaunchKernelGGL((adj_fields_kernel<Q>), dim3(ntn), dim3(WN * Q), 0, st, Pn, A);
   EVLB_HIP(hipGetLastError());
-  A.part = part + (size_t)(2 * vjp_index + 1) * 2 * nta;
+  A.part = part + ((size_t)vjp_index * (ntn + nta) + ntn) * 2;
   hipLaunchKernelGGL((adj_node_kernel<Q>), dim3(nta), dim3(64 * NWT), 0, st, P, A, P.vel, final_reduce ? 1 : 0,
-                     (const double*)part, 6 * nta, dparams);
+                     (const double*)part, 3 * (ntn + nta), dparams);
   EVLB_HIP(hipGetLastError());
   hipLaunchKernelGGL((adj_column_kernel<Q>), dim3(nta * (2 * Q / ADJ_ROWS)), dim3(64), 0, st, P, A, P.vel);
   EVLB_HIP(hipGetLastError());
