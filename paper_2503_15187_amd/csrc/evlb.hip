@@ -1710,10 +1710,8 @@ int launch_vjp(evlb_ctx* c, const double* f, const double* mom, const double* v,
   hipLaunchKernelGGL((adj_fields_kernel<Q>), dim3(ntn), dim3(WN * Q), 0, st, Pn, A);
   EVLB_HIP(hipGetLastError());
   A.part = part + ((size_t)vjp_index * (ntn + nta) + ntn) * 2;
-  hipLaunchKernelGGL((adj_node_kernel<Q>), dim3(nta), dim3(64 * NWT), 0, st, P, A, P.vel, final_reduce ? 1 : 0,
-                     (const double*)part, 3 * (ntn + nta), dparams);
-  EVLB_HIP(hipGetLastError());
-  hipLaunchKernelGGL((adj_column_kernel<Q>), dim3(nta * (2 * Q / ADJ_ROWS)), dim3(64), 0, st, P, A, P.vel);
+  hipLaunchKernelGGL((adj_column_kernel<Q>), dim3(nta * (2 * Q / NCW)), dim3(64 * NCW), 0, st, P, A,
+                     final_reduce ? 1 : 0, (const double*)part, 3 * (ntn + nta), dparams);
   EVLB_HIP(hipGetLastError());
   return EVLB_OK;
 }
