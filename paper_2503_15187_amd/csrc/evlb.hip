@@ -87,7 +87,7 @@ struct StageArgs {
 
 // Classical WENO-5 (Jiang & Shu) face value from the five upwind-ordered
 // values v0..v4 = f_{i-2}..f_{i+2}; alpha_r = d_r/(eps+beta_r)^2 combined
-// over a common denominator (one division).
+// over a common denominator (one reciprocal).
 __device__ __forceinline__ double weno5(double v0, double v1, double v2, double v3, double v4,
                                         double eps) {
   const double q0 = (2.0 * v0 - 7.0 * v1 + 11.0 * v2) * (1.0 / 6.0);
@@ -103,7 +103,12 @@ __device__ __forceinline__ double weno5(double v0, double v1, double v2, double 
   double t1 = eps + b1; t1 *= t1;
   double t2 = eps + b2; t2 *= t2;
   const double w0 = 0.1 * t1 * t2, w1 = 0.6 * t0 * t2, w2 = 0.3 * t0 * t1;
-  return (w0 * q0 + w1 * q1 + w2 * q2) / (w0 + w1 + w2);
+  // divide through the hardware reciprocal and two Newton steps r <- r (2 - d r)
+  const double den = w0 + w1 + w2;
+  double r = __builtin_amdgcn_rcp(den);
+  r = fma(r, fma(-den, r, 1.0), r);
+  r = fma(r, fma(-den, r, 1.0), r);
+  return (w0 * q0 + w1 * q1 + w2 * q2) * r;
 }
 
 // Launch shape of the stage kernel: tiles of W nodes, NG groups of
