@@ -524,6 +524,26 @@ typedef double dbl4 __attribute__((ext_vector_type(4)));
 // ---------------------------------------------------------------------------
 constexpr int WN = 16;
 
+// Sum of v over the four lanes j, j + 16, j + 32, j + 48 (every lane gets
+// it): the cross-row swaps of gfx950 exchange 16-lane rows (pairs 0-1, 2-3)
+// and 32-lane halves on the VALU.
+__device__ __forceinline__ double row4_sum(double v) {
+  const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+  const unsigned lo = (unsigned)b, hi = (unsigned)(b >> 32);
+  const auto l16 = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+  const auto h16 = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+  const double a = __builtin_bit_cast(double, (unsigned long long)l16[0] | ((unsigned long long)h16[0] << 32));
+  const double c = __builtin_bit_cast(double, (unsigned long long)l16[1] | ((unsigned long long)h16[1] << 32));
+  const double s = a + c;  // rows 0 + 1 in rows 0, 1; rows 2 + 3 in rows 2, 3
+  const unsigned long long sb = __builtin_bit_cast(unsigned long long, s);
+  const unsigned slo = (unsigned)sb, shi = (unsigned)(sb >> 32);
+  const auto l32 = __builtin_amdgcn_permlane32_swap(slo, slo, false, false);
+  const auto h32 = __builtin_amdgcn_permlane32_swap(shi, shi, false, false);
+  const double x = __builtin_bit_cast(double, (unsigned long long)l32[0] | ((unsigned long long)h32[0] << 32));
+  const double y = __builtin_bit_cast(double, (unsigned long long)l32[1] | ((unsigned long long)h32[1] << 32));
+  return x + y;
+}
+
 template <int Q>
 struct SmemN {
   double f[2 * Q][WN + 2 * HF];  // F rows then G rows, tile + WENO halo
@@ -718,13 +738,15 @@ __device__ void stage_tile_narrow(const DevParams& P, const StageArgs& A, int ti
     if (m <= m1) s0 += S.cf[m - 1] * (S.n[cn + m] - S.n[cn - m]);
     S.fpart[k][j] = s0 + s1;
   }
-  if ((P.term_mask & EVLB_TERM_ADV) && tid >= W + 4 && tid < NT - W) {
-    // faces on the threads without contact-value or Hermite work
+  // faces on the threads without contact-value or Hermite work; with six or
+  // more wavefronts the contact-value wavefront takes none
+  constexpr int WS = NT >= 384 ? 64 : W + 4;
+  if ((P.term_mask & EVLB_TERM_ADV) && tid >= WS && tid < NT - W) {
     constexpr int NFACE = 2 * Q * (W + 1);
-    constexpr int NFT = NT - 2 * W - 4;
+    constexpr int NFT = NT - W - WS;
 #pragma unroll
     for (int i = 0; i < (NFACE + NFT - 1) / NFT; ++i) {
-      const int idx = tid - (W + 4) + i * NFT;
+      const int idx = tid - WS + i * NFT;
       if (idx < NFACE) {
         const int r = idx / (W + 1);
         const int jf = idx - r * (W + 1);  // face i0 + jf - 1/2
@@ -857,10 +879,7 @@ __device__ void stage_tile_narrow(const DevParams& P, const StageArgs& A, int ti
   }
   // the four velocities of a node within a wavefront: lanes j, j + 16, j + 32, j + 48
 #pragma unroll
-  for (int m = 0; m < 6; ++m) {
-    pm[m] += __shfl_xor(pm[m], 16);
-    pm[m] += __shfl_xor(pm[m], 32);
-  }
+  for (int m = 0; m < 6; ++m) pm[m] = row4_sum(pm[m]);
   if (lane < W) {
 #pragma unroll
     for (int m = 0; m < 6; ++m) S.red[wave][m][j] = pm[m];
