@@ -537,6 +537,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
                                                   const double* __restrict__ meq,
                                                   const double* __restrict__ dpm) {
   __shared__ double s_ey[4][16][Q];  // per wave: e_l(u_y) of its 16 nodes
+  __shared__ double s_pc[4][4][4][64];  // per wave: row polynomial coefficients [al be ga ne][j][lane]
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int nd = lane & 15, g = lane >> 4;
   const int nseg = (D.nx + 63) >> 6;
@@ -615,7 +616,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
       for (int j = 0; j < 4; ++j) wb[p][j] = bload(PLANE(wd, j, p), vo);
 
     // row polynomials of the collision terms
-    double al[4], be[4], ga[4], ne[4], de, nu, Fx, Fy, uy;
+    // the row polynomials live in LDS (registers are the occupancy limit)
+    double(*pc)[4][64] = s_pc[wave];
+    double de, nu, Fx, Fy, uy;
     {
       const double n = fd[F_N * Nd + node], ux = fd[F_UX * Nd + node], T = fd[F_T * Nd + node];
       uy = fd[F_UY * Nd + node];
@@ -640,14 +643,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
         const double xx = pkv[j] - ux;
         const double t0 = xx * xx * invT - th0;
         const double r = xx * Sx + C;
-        al[j] = nu + pAx * xx + t0 * r + W4 * uxx * xx * xx;
-        be[j] = pAy + t0 * Sy + Uc * xx;
-        ga[j] = invT * r + W4 * uyy;
-        ne[j] = tf * n * ex[j];
-      }
-      if (!j0 && !j1) {
-#pragma unroll
-        for (int j = 0; j < 4; ++j) ne[j] = 0.0;
+        pc[0][j][lane] = nu + pAx * xx + t0 * r + W4 * uxx * xx * xx;
+        pc[1][j][lane] = pAy + t0 * Sy + Uc * xx;
+        pc[2][j][lane] = invT * r + W4 * uyy;
+        pc[3][j][lane] = (j0 || j1) ? tf * n * ex[j] : 0.0;
       }
     }
     // velocity sums of the new state: 1, p_x, p_y (both passes), p_x^2,
@@ -673,9 +672,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
       const double pl = vl[l];
       const double xy = pl - uy;
       const double eyl = eyv[l];
+      // an opaque copy of the lane index per column keeps the polynomial
+      // coefficients in LDS instead of being hoisted back into registers
+      int pli = lane;
+      asm volatile("" : "+v"(pli));
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        double R = ne[j] * eyl * (al[j] + xy * (be[j] + xy * (ga[j] + de * xy))) - nu * M[j][l];
+        double R = pc[3][j][pli] * eyl * (pc[0][j][pli] + xy * (pc[1][j][pli] + xy * (pc[2][j][pli] + de * xy))) -
+                   nu * M[j][l];
         if (FRC) {
           double d0 = 0.0, d1 = 0.0;
 #pragma unroll
