@@ -538,6 +538,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
                                                   const double* __restrict__ dpm) {
   __shared__ double s_ey[4][16][Q];  // per wave: e_l(u_y) of its 16 nodes
   __shared__ double s_pc[4][4][4][64];  // per wave: row polynomial coefficients [al be ga ne][j][lane]
+  __shared__ double s_aop[4][64];       // MFMA A operands Dp[nd][g + 4 b] (the same for every wave)
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int nd = lane & 15, g = lane >> 4;
   const int nseg = (D.nx + 63) >> 6;
@@ -573,11 +574,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
       if ((k & 3) == g) ex[k >> 2] = s;
     }
   }
-  double pkv[4], aop[4];
+  double pkv[4];
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     pkv[j] = vel[g + 4 * j];
-    aop[j] = dpm[nd * Q + g + 4 * j];
+    if (wave == 0) s_aop[j][lane] = dpm[nd * Q + g + 4 * j];
   }
   __syncthreads();
   const double* eyv = &s_ey[wave][nd][0];
@@ -662,20 +663,21 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
 #pragma unroll
         for (int j = 0; j < 4; ++j) wb[l % PF][j] = bload(PLANE(wd, j, l + PF), vo);
       }
+      // an opaque copy of the lane index per column keeps the MFMA operands
+      // and polynomial coefficients in LDS instead of being hoisted back into
+      // registers
+      int pli = lane;
+      asm volatile("" : "+v"(pli));
       dbl4 acc = {0.0, 0.0, 0.0, 0.0};
       if (FRC) {
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(aop[0], M[0][l], acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(aop[1], M[1][l], acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(aop[2], M[2][l], acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(aop[3], M[3][l], acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(s_aop[0][pli], M[0][l], acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(s_aop[1][pli], M[1][l], acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(s_aop[2][pli], M[2][l], acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(s_aop[3][pli], M[3][l], acc, 0, 0, 0);
       }
       const double pl = vl[l];
       const double xy = pl - uy;
       const double eyl = eyv[l];
-      // an opaque copy of the lane index per column keeps the polynomial
-      // coefficients in LDS instead of being hoisted back into registers
-      int pli = lane;
-      asm volatile("" : "+v"(pli));
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         double R = pc[3][j][pli] * eyl * (pc[0][j][pli] + xy * (pc[1][j][pli] + xy * (pc[2][j][pli] + de * xy))) -
