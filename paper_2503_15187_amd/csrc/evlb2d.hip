@@ -365,14 +365,18 @@ struct AdvStrip {
   double rw[4];       // raw rows, slot = (row - y0) mod 4
   Tri ct[4];          // triples of rows, slot = (row - y0) mod 4
   double fyl;         // face between rows y - 1 and y
+  double nxr;         // row y + 3, loaded one row ahead
+  double f0n;         // f^n of row y, loaded one row ahead
 };
 
-// Row y = y0 + r with r = PH (mod 4): load row y + 3, build the triple of row
-// y + 2, the face between rows y and y + 1, the two x faces of row y, update.
+// Row y = y0 + r with r = PH (mod 4): take row y + 3 (loaded one row ahead)
+// and load row y + 4, build the triple of row y + 2, the face between rows y
+// and y + 1, the two x faces of row y, update.
 template <bool PX, bool PY, int PH>
 __device__ __forceinline__ void adv_row(AdvStrip& S, const AdvArgs& A, int r) {
   constexpr int s0 = PH & 3, s1 = (PH + 1) & 3, s2 = (PH + 2) & 3, s3 = (PH + 3) & 3;
-  S.rw[s3] = S.fs[(long long)S.yr * S.nx + S.xc];
+  S.rw[s3] = S.nxr;
+  S.nxr = S.fs[(long long)S.yr * S.nx + S.xc];
   if (++S.yr == S.ny) S.yr = 0;
   S.ct[s2] = tri_dir<PY>(S.rw[s1], S.rw[s2], S.rw[s3]);
   // upwind below: triples of rows y - 1, y, y + 1; above: y + 2, y + 1, y
@@ -391,10 +395,13 @@ __device__ __forceinline__ void adv_row(AdvStrip& S, const AdvArgs& A, int r) {
   }
   const double fxr = __shfl_down(fxl, 1);
   const int y = S.y0 + r;
+  const double f0v = A.first ? c0 : S.f0n;
+  // f^n of the next row of this strip (W may alias f^n: only rows this
+  // wavefront owns are read ahead)
+  if (!A.first && S.outcol && r + 1 < AR && y + 1 < S.ny) S.f0n = S.f0[(long long)(y + 1) * S.nx + S.xc];
   if (S.outcol && y < S.ny) {
     const long long node = (long long)y * S.nx + S.xc;
     const double adv = fma(S.pxi, fxl - fxr, S.pyi * (S.fyl - fyr));
-    const double f0v = A.first ? c0 : S.f0[node];
     S.W[node] = fma(A.c, adv, fma(A.b, c0, A.a * f0v));
   }
   S.fyl = fyr;
@@ -416,6 +423,10 @@ __device__ __forceinline__ void adv_strip(AdvStrip& S, const AdvArgs& A) {
   S.rw[0] = p[3];
   S.rw[1] = p[4];
   S.rw[2] = p[5];
+  S.nxr = S.fs[(long long)S.yr * S.nx + S.xc];  // row y0 + 3
+  if (++S.yr == S.ny) S.yr = 0;
+  S.f0n = 0.0;
+  if (!A.first && S.outcol && S.y0 < S.ny) S.f0n = S.f0[(long long)S.y0 * S.nx + S.xc];
   // face between rows y0 - 1 and y0
   S.fyl = PY ? face3(S.ct[2].bp, S.ct[2].qp, S.ct[3].b0, S.ct[3].q0, S.ct[0].bm, S.ct[0].qm, S.eps4)
              : face3(S.ct[1].bp, S.ct[1].qp, S.ct[0].b0, S.ct[0].q0, S.ct[3].bm, S.ct[3].qm, S.eps4);
