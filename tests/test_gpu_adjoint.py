@@ -80,7 +80,7 @@ def test_adjoint_step_equals_transposed_jacobian(mask):
         assert abs(dp[idx] - r) <= 1e-10 * max(1.0, abs(r)), (which, dp[idx], r)
 
 
-@pytest.mark.parametrize("Q,N,dx", [(16, 150, 1 / 8), (24, 130, 1 / 8), (16, 200, 1 / 4)])
+@pytest.mark.parametrize("Q,N,dx", [(16, 150, 1 / 8), (24, 130, 1 / 8), (16, 200, 1 / 4), (8, 140, 1 / 8)])
 def test_adjoint_dot_product(Q, N, dx):
     """<J^T lam, v> (GPU adjoint) = <lam, J v> (oracle complex step along v)."""
     dt = 0.2 * dx / 8.6

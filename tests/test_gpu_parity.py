@@ -110,6 +110,32 @@ def test_one_and_ten_steps_match_oracle(mode, tile):
         assert s.status() == 0
 
 
+@pytest.mark.parametrize("tile", [16, 63, 64])
+def test_q8_rhs_and_steps_match_oracle(tile):
+    """Q = 8 (two wavefronts per narrow tile, two MFMA chains on one of them):
+    the phase-separation state on its own 8-node velocity set."""
+    c, n, u, T = case_phase()
+    c = dict(c, Q=8)
+    print(f"q8 case nx={c['nx']} tile={tile}", flush=True)
+    tb = oracle_tables(c)
+    F, G = nonequilibrium(*step1d.initial_state(n, u + 0.02 * np.sin(np.arange(len(n)) / 7.0), T, tb), tb)
+    LF, LG = step1d.rhs(F, G, tb)
+    s = solver(c, tile_nodes=tile)
+    L = s.rhs(td(np.stack([F, G]))).cpu().numpy()
+    assert rel(L, [LF, LG]) < 1e-11
+    for mode in (1, 2):
+        F0, G0 = step1d.initial_state(n, u, T, tb)
+        s = solver(c, exec_mode=mode, tile_nodes=tile)
+        f = s.equilibrium(td(n), td(u), td(T))
+        s.step(f, 1)
+        F1, G1 = step1d.rk3_step(F0, G0, tb)
+        assert rel(f.cpu().numpy(), [F1, G1]) < 1e-11
+        s.step(f, 9)
+        F10, G10 = step1d.run(F1, G1, tb, 9)
+        assert rel(f.cpu().numpy(), [F10, G10]) < 1e-10
+        assert s.status() == 0
+
+
 def test_phase_separation_1000_steps_match_oracle():
     """Full phase-separation workload: 256 nodes, Q = 16, 1000 steps."""
     c, n, u, T = case_phase()
