@@ -111,16 +111,16 @@ __device__ __forceinline__ double weno5(double v0, double v1, double v2, double 
   return (w0 * q0 + w1 * q1 + w2 * q2) * r;
 }
 
-// Launch shape of the stage kernel: tiles of W nodes, NG groups of
-// velocities (thread = node j x group g, NT = W * NG threads).  With W = 64
-// a velocity group is uniform over a wavefront and the constant tables are
-// read through the scalar cache; narrower tiles keep them in LDS (the
-// 16-node shape has its own tile function, stage_tile_narrow).
+// Launch shape of the wide stage kernel: tiles of W = 64 nodes, NG groups of
+// velocities (thread = node j x group g, NT = W * NG threads).  A velocity
+// group is uniform over a wavefront, so the constant tables are read through
+// the scalar cache.  (The 16-node shape has its own tile function,
+// stage_tile_narrow.)
 template <int Q, int W, int NG>
 struct Shape {
   static constexpr int NT = W * NG;
   static constexpr int VPT = Q / NG;
-  static constexpr bool UNIFORM = (W % 64) == 0;
+  static_assert(W % 64 == 0, "a velocity group spans whole wavefronts");
   static_assert(Q % NG == 0, "velocity groups must divide q");
   static_assert(NG >= 2, "two node groups are needed for the field phase");
   static_assert(NT <= 1024, "workgroup too large");
@@ -141,7 +141,6 @@ struct Smem {
     double msum[6][W];             // velocity moments of the new state
   };
   double nf[NFIELD][W];
-  double tab[Shape<Q, W, NG>::UNIFORM ? 1 : 2 * Q * Q + Q];  // meq, dpm, vel
   double sav[2 * MS_MAX + 1];      // averaging weights
   double cf[MF_MAX];               // EV1 force taps
 };
@@ -152,15 +151,13 @@ __device__ __forceinline__ int wrapi(int i, int n) {
   return i;
 }
 
-// Constant tables into LDS: the averaging weights and force taps always, the
-// velocity tables for the narrow shapes.  All loads are issued before the
-// first LDS write, so the copy costs one memory round trip.
+// The averaging weights and force taps into LDS.  All loads are issued
+// before the first LDS write, so the copy costs one memory round trip.
 template <int Q, int W, int NG>
 __device__ __forceinline__ void load_tables(const DevParams& P, Smem<Q, W, NG>& S) {
   constexpr int NT = Shape<Q, W, NG>::NT;
-  constexpr int NTAB = Shape<Q, W, NG>::UNIFORM ? 0 : 2 * Q * Q + Q;
   constexpr int NSAV = 2 * MS_MAX + 1;
-  constexpr int NALL = NTAB + NSAV + MF_MAX;
+  constexpr int NALL = NSAV + MF_MAX;
   constexpr int L = (NALL + NT - 1) / NT;
   const int tid = threadIdx.x;
   double v[L];
@@ -171,19 +168,15 @@ __device__ __forceinline__ void load_tables(const DevParams& P, Smem<Q, W, NG>& 
     // branches would be serialised by the register they share)
     const double* src = nullptr;
     int si = 0;
-    if (NTAB > 0 && e < Q * Q) { src = P.meq; si = e; }
-    else if (NTAB > 0 && e < 2 * Q * Q) { src = P.dpm; si = e - Q * Q; }
-    else if (e < NTAB) { src = P.vel; si = e - 2 * Q * Q; }
-    else if (e < NTAB + 2 * P.ms + 1) { src = P.savg; si = e - NTAB; }
-    else if (e >= NTAB + NSAV && e < NTAB + NSAV + P.mf) { src = P.cfor; si = e - NTAB - NSAV; }
+    if (e < 2 * P.ms + 1) { src = P.savg; si = e; }
+    else if (e >= NSAV && e < NSAV + P.mf) { src = P.cfor; si = e - NSAV; }
     v[i] = src ? src[si] : 0.0;
   }
 #pragma unroll
   for (int i = 0; i < L; ++i) {
     const int e = tid + i * NT;
-    if (e < NTAB) S.tab[e] = v[i];
-    else if (e < NTAB + NSAV) S.sav[e - NTAB] = v[i];
-    else if (e < NALL) S.cf[e - NTAB - NSAV] = v[i];
+    if (e < NSAV) S.sav[e] = v[i];
+    else if (e < NALL) S.cf[e - NSAV] = v[i];
   }
   __syncthreads();
 }
@@ -200,7 +193,7 @@ __device__ void stage_tile(const DevParams& P, const StageArgs& A, int tile, Sme
   const long long ntot = P.ntot;
   const int hn = P.hn;
   const int j = tid % W;
-  const int g = SH::UNIFORM ? __builtin_amdgcn_readfirstlane(tid / W) : tid / W;
+  const int g = __builtin_amdgcn_readfirstlane(tid / W);
   const int kbase = g * VPT;
   const bool valid = (i0 + j) < nsys;
   const long long gnode = off + i0 + j;
@@ -384,9 +377,9 @@ __device__ void stage_tile(const DevParams& P, const StageArgs& A, int tile, Sme
   __syncthreads();
 
   // ---- 4. update -----------------------------------------------------------
-  const double* meq = SH::UNIFORM ? P.meq : S.tab;
-  const double* dpm = SH::UNIFORM ? P.dpm : S.tab + Q * Q;
-  const double* vel = SH::UNIFORM ? P.vel : S.tab + 2 * Q * Q;
+  const double* meq = P.meq;
+  const double* dpm = P.dpm;
+  const double* vel = P.vel;
   double pm[6] = {0, 0, 0, 0, 0, 0};
   {
     const double u = S.nf[NF_U][j], T = S.nf[NF_T][j];
