@@ -51,7 +51,7 @@
 extern "C" {
 #endif
 
-#define EVLB_ABI_VERSION 3
+#define EVLB_ABI_VERSION 4
 
 enum {
   EVLB_OK = 0,
@@ -119,6 +119,13 @@ typedef struct {
                             instead of the moment temperature, so grad T = 0
                             and the energy is not conserved.  0: the thermal
                             model.  Not available with adjoint = 1.          */
+  const double* T_iso_sys; /* NULL, or host [n_sys]: a fixed temperature per
+                            system (>= 0, finite; 0 = thermal), overriding
+                            T_iso, so that a sweep of the Sec. III A
+                            stationary interfaces over T runs as one batch.
+                            Copied by evlb_init.  dim 1 only; not available
+                            with adjoint = 1 (EVLB_EUNSUPPORTED).  Adds
+                            8 bytes per node to the workspace.              */
 } evlb_params;
 
 typedef struct evlb_ctx evlb_ctx; /* opaque, host memory */

@@ -69,6 +69,7 @@ struct DevParams {
   double sigma;
   double weno_eps, g_ext, two_a, kappa;
   double T_iso;    // > 0: isothermal, the temperature the next stage sees
+  const double* tiso;  // per node: the isothermal temperature of its system (0 = thermal), or null
   int force_model, term_mask;
   int* status;     // [0] non-finite latch, [1] barrier abort latch
   unsigned* bar;   // [0] arrival count, [1] generation
@@ -247,6 +248,9 @@ __device__ void stage_tile(const DevParams& P, const StageArgs& A, int tile, Sme
   }
   double qj = 0.0;
   if (tid >= W && tid < 2 * W) qj = mn[3 * ntot + off + wrapi(i0 + j, nsys)];
+  // isothermal temperature of the own node's system, read with the tile
+  double tiso = P.T_iso;
+  if (P.tiso && tid < W && valid) tiso = P.tiso[gnode];
 #pragma unroll
   for (int i = 0; i < LF; ++i) {
     const int idx = tid + i * NT;
@@ -491,7 +495,7 @@ __device__ void stage_tile(const DevParams& P, const StageArgs& A, int tile, Sme
     const double q = 0.5 * x3 + S.msum[5][tid] - u * S.msum[4][tid];
     A.mom_out[gnode] = n;
     A.mom_out[ntot + gnode] = u;
-    A.mom_out[2 * ntot + gnode] = P.T_iso > 0.0 ? P.T_iso : T;
+    A.mom_out[2 * ntot + gnode] = tiso > 0.0 ? tiso : T;
     A.mom_out[3 * ntot + gnode] = q;
     if (!(n > 0.0) || !(T > 0.0) || !isfinite(n) || !isfinite(T) || !isfinite(q) || !isfinite(u))
       P.status[0] = 1;
@@ -638,6 +642,9 @@ __device__ void stage_tile_narrow(const DevParams& P, const StageArgs& A, int ti
     Tv = mn[2 * ntot + node];
     qv = mn[3 * ntot + node];
   }
+  // isothermal temperature of the own node's system (moment threads)
+  double tiso = P.T_iso;
+  if (P.tiso && tid < W && valid) tiso = P.tiso[gnode];
   // averaging weights and force taps: threads NT - 97 .. NT - 1
   constexpr int NSAV = 2 * MS_MAX + 1;
   const int e = tid - (NT - NSAV - MF_MAX);
@@ -900,7 +907,7 @@ __device__ void stage_tile_narrow(const DevParams& P, const StageArgs& A, int ti
     const double q = 0.5 * x3 + ms[5] - u * ms[4];
     A.mom_out[gnode] = n;
     A.mom_out[ntot + gnode] = u;
-    A.mom_out[2 * ntot + gnode] = P.T_iso > 0.0 ? P.T_iso : T;
+    A.mom_out[2 * ntot + gnode] = tiso > 0.0 ? tiso : T;
     A.mom_out[3 * ntot + gnode] = q;
     if (!(n > 0.0) || !(T > 0.0) || !isfinite(n) || !isfinite(T) || !isfinite(q) || !isfinite(u))
       P.status[0] = 1;
@@ -919,7 +926,7 @@ __global__ __launch_bounds__(W * NG) void stage_kernel(DevParams P, StageArgs A)
                  "s"(P.ntiles), "s"(P.single), "s"(P.ms), "s"(P.mf), "s"(P.hn), "s"(P.ntot), "s"(P.force_model),
                  "s"(P.term_mask));
     asm volatile("" ::"s"(P.inv_dx), "s"(P.dt), "s"(P.b), "s"(P.eta_c), "s"(P.mu0c), "s"(P.weno_eps), "s"(P.g_ext),
-                 "s"(P.two_a), "s"(P.kappa), "s"(P.T_iso));
+                 "s"(P.two_a), "s"(P.kappa), "s"(P.T_iso), "s"(P.tiso));
     asm volatile("" ::"s"(A.f_prev), "s"(A.f_n), "s"(A.f_out), "s"(A.mom_in), "s"(A.mom_out), "s"(A.alpha),
                  "s"(A.beta), "s"(A.first), "s"(A.rhs_mode));
     for (int t = blockIdx.x; t < P.ntiles; t += gridDim.x) stage_tile_narrow<Q>(P, A, t, S);
@@ -1017,6 +1024,7 @@ __device__ void stage_tile_col(const DevParams& P, const StageArgs& A, int tile,
     tv[i] = src ? src[si] : 0.0;
   }
   const double qj = valid ? mn[3 * ntot + gnode] : 0.0;
+  const double tiso = P.tiso && valid ? P.tiso[gnode] : P.T_iso;
 #pragma unroll
   for (int i = 0; i < LN; ++i) {
     const int c = lane + 64 * i;
@@ -1199,7 +1207,7 @@ __device__ void stage_tile_col(const DevParams& P, const StageArgs& A, int tile,
     const double q1 = 0.5 * x3 + pm[5] - u1 * pm[4];
     A.mom_out[gnode] = n1;
     A.mom_out[ntot + gnode] = u1;
-    A.mom_out[2 * ntot + gnode] = P.T_iso > 0.0 ? P.T_iso : T1;
+    A.mom_out[2 * ntot + gnode] = tiso > 0.0 ? tiso : T1;
     A.mom_out[3 * ntot + gnode] = q1;
     if (!(n1 > 0.0) || !(T1 > 0.0) || !isfinite(n1) || !isfinite(T1) || !isfinite(q1) || !isfinite(u1))
       P.status[0] = 1;
@@ -1356,7 +1364,8 @@ __global__ __launch_bounds__(256) void moments_kernel(DevParams P, const double*
   n_out[i] = n;
   u_out[i] = u;
   // as the input of a stage, an isothermal run sees its fixed temperature
-  T_out[i] = stage_input && P.T_iso > 0.0 ? P.T_iso : T;
+  const double tiso = stage_input ? (P.tiso ? P.tiso[i] : P.T_iso) : 0.0;
+  T_out[i] = tiso > 0.0 ? tiso : T;
   if (q_out) q_out[i] = q;
 }
 
@@ -1397,7 +1406,7 @@ constexpr int WIDE = 64;    // tile width for large grids
 constexpr int NARROW = WN;  // tile width for grids too small to fill the chip
 
 struct Layout {
-  size_t tables, tiles_wide, tiles_narrow, tiles_col, tiles_adj, f1, f2, momA, momB, status;
+  size_t tables, tiles_wide, tiles_narrow, tiles_col, tiles_adj, f1, f2, momA, momB, status, tiso;
   size_t adj_g, adj_mu2, adj_mu1, adj_fa, adj_fb, adj_mom, adj_part, adj_lam, total;
   long long ntot;
   int ntiles_wide, ntiles_narrow, ntiles_col, ntiles_adj, ms, mf;
@@ -1421,7 +1430,7 @@ bool is_even_multiple(double a, double dx, int* m, double tol = 1e-9) {
 int validate(const evlb_params* p) {
   if (!p) return EVLB_EINVAL;
   if (p->abi_version != EVLB_ABI_VERSION) return EVLB_EINVAL;
-  if (p->dim == 2) return evlb2d::validate(p);
+  if (p->dim == 2) return p->T_iso_sys ? EVLB_EUNSUPPORTED : evlb2d::validate(p);
   if (p->dim != 1) return EVLB_EUNSUPPORTED;
   if (p->n_sys < 1 || !p->nx) return EVLB_EINVAL;
   long long ntot = 0;
@@ -1443,6 +1452,13 @@ int validate(const evlb_params* p) {
   if (p->adjoint && p->force_model == EVLB_FORCE_EV2) return EVLB_EUNSUPPORTED;
   if (!(p->T_iso >= 0.0) || !std::isfinite(p->T_iso)) return EVLB_EINVAL;
   if (p->adjoint && p->T_iso > 0.0) return EVLB_EUNSUPPORTED;
+  if (p->T_iso_sys) {
+    for (int s = 0; s < p->n_sys; ++s) {
+      const double t = p->T_iso_sys[s];
+      if (!(t >= 0.0) || !std::isfinite(t)) return EVLB_EINVAL;
+      if (p->adjoint && t > 0.0) return EVLB_EUNSUPPORTED;
+    }
+  }
   if (p->tile_nodes != 0 && p->tile_nodes != WIDE && p->tile_nodes != NARROW && p->tile_nodes != WC)
     return EVLB_EINVAL;
   int ms, mf = 0;
@@ -1490,6 +1506,11 @@ Layout make_layout(const evlb_params* p) {
   L.momA = off; off += mbytes;
   L.momB = off; off += mbytes;
   L.status = off; off += 256;
+  L.tiso = 0;
+  if (p->T_iso_sys) {
+    L.tiso = off;
+    off += align256(sizeof(double) * (size_t)L.ntot);
+  }
   if (p->adjoint) {
     L.adj_g = off; off += fbytes;
     L.adj_mu2 = off; off += fbytes;
@@ -1511,6 +1532,7 @@ struct evlb_ctx {
   evlb_params p;
   std::vector<int32_t> nx;
   std::vector<double> vel;
+  std::vector<double> tiso;  // per-system isothermal temperatures (copy of T_iso_sys)
   Layout L;
   DevParams dp;  // tiles/ntiles of the wide shape; launches patch them
   char* ws;
@@ -1904,6 +1926,8 @@ int evlb_init(const evlb_params* params, void* d_workspace, size_t ws_bytes, voi
   c->p = *params;
   c->nx.assign(params->nx, params->nx + params->n_sys);
   c->p.nx = c->nx.data();
+  if (params->T_iso_sys) c->tiso.assign(params->T_iso_sys, params->T_iso_sys + params->n_sys);
+  c->p.T_iso_sys = params->T_iso_sys ? c->tiso.data() : nullptr;
   c->L = L;
   c->ws = (char*)d_workspace;
   if (hipGetDevice(&c->device) != hipSuccess) { delete c; return EVLB_EHIP; }
@@ -1951,6 +1975,18 @@ int evlb_init(const evlb_params* params, void* d_workspace, size_t ws_bytes, voi
     delete c;
     return EVLB_EHIP;
   }
+  if (params->T_iso_sys) {
+    // the per-system temperatures expanded to one value per node
+    std::vector<double> tn_node((size_t)L.ntot);
+    size_t o = 0;
+    for (int s = 0; s < params->n_sys; ++s)
+      for (int i = 0; i < params->nx[s]; ++i) tn_node[o++] = params->T_iso_sys[s];
+    if (hipMemcpy(c->ws + L.tiso, tn_node.data(), tn_node.size() * sizeof(double), hipMemcpyHostToDevice) !=
+        hipSuccess) {
+      delete c;
+      return EVLB_EHIP;
+    }
+  }
   (void)st;
   DevParams& d = c->dp;
   d.vel = tab;
@@ -1985,6 +2021,7 @@ int evlb_init(const evlb_params* params, void* d_workspace, size_t ws_bytes, voi
   d.force_model = params->force_model;
   d.term_mask = params->term_mask;
   d.T_iso = params->T_iso;
+  d.tiso = params->T_iso_sys ? (const double*)(c->ws + L.tiso) : nullptr;
   d.status = (int*)(c->ws + L.status);
   d.bar = (unsigned*)(c->ws + L.status + 64);
   *out = c;

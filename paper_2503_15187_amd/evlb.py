@@ -14,7 +14,7 @@ import torch
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libevlb.so")
 
-EVLB_ABI_VERSION = 3
+EVLB_ABI_VERSION = 4
 EVLB_OK, EVLB_EINVAL, EVLB_ECFL, EVLB_EWORKSPACE, EVLB_EHIP, EVLB_ENONFINITE, EVLB_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 EVLB_FORCE_EV1, EVLB_FORCE_EV2, EVLB_FORCE_NONE = 0, 1, 2
 EVLB_TERM_ADV, EVLB_TERM_FORCE, EVLB_TERM_J0, EVLB_TERM_J1, EVLB_TERM_ALL = 1, 2, 4, 8, 15
@@ -43,6 +43,7 @@ class evlb_params(ctypes.Structure):
         ("adjoint", ctypes.c_int32),
         ("ny", ctypes.c_int32),
         ("T_iso", ctypes.c_double),
+        ("T_iso_sys", ctypes.POINTER(ctypes.c_double)),
     ]
 
 
@@ -103,19 +104,27 @@ def _check(code, what):
 
 def make_params(q, dx, dt, nx, sigma=1.0, phi_sigma=1.0, gamma=6.0, r_cut=5.0,
                 force_model=EVLB_FORCE_EV1, term_mask=EVLB_TERM_ALL, weno_eps=1e-6,
-                g_ext=0.0, exec_mode=EVLB_EXEC_AUTO, tile_nodes=0, adjoint=0, ny=0, T_iso=0.0):
+                g_ext=0.0, exec_mode=EVLB_EXEC_AUTO, tile_nodes=0, adjoint=0, ny=0, T_iso=0.0,
+                T_iso_sys=None):
     """evlb_params for one or several periodic 1D systems (nx: int or list),
     or, with ny > 0, one periodic nx x ny 2D system (dim 2).  T_iso > 0
-    selects the isothermal model at that temperature.  The returned
-    structure keeps its nx array alive."""
+    selects the isothermal model at that temperature; T_iso_sys (one value
+    per system, 0 = thermal) sets it per system.  The returned structure
+    keeps its arrays alive."""
     nxs = [int(nx)] if isinstance(nx, (int,)) else [int(v) for v in nx]
     arr = (ctypes.c_int32 * len(nxs))(*nxs)
     dim = 2 if ny else 1
     p = evlb_params(EVLB_ABI_VERSION, dim, len(nxs), arr, int(q), float(dx), float(dt), float(sigma),
                     float(phi_sigma), float(gamma), float(r_cut), int(force_model), int(term_mask),
                     float(weno_eps), float(g_ext), int(exec_mode), int(tile_nodes), int(adjoint), int(ny),
-                    float(T_iso))
+                    float(T_iso), None)
     p._nx_keepalive = arr
+    if T_iso_sys is not None:
+        if len(T_iso_sys) != len(nxs):
+            raise ValueError("T_iso_sys needs one temperature per system")
+        ts = (ctypes.c_double * len(nxs))(*[float(v) for v in T_iso_sys])
+        p.T_iso_sys = ts
+        p._tiso_keepalive = ts
     return p
 
 

@@ -53,6 +53,9 @@ def test_validate_accepts_workload_parameters():
     (dict(sigma=-1.0), E.EVLB_EINVAL),
     (dict(T_iso=-0.5), E.EVLB_EINVAL),
     (dict(T_iso=0.6, adjoint=1), E.EVLB_EUNSUPPORTED),
+    (dict(nx=[256, 300], T_iso_sys=[0.6, -0.1]), E.EVLB_EINVAL),
+    (dict(nx=[256, 300], T_iso_sys=[0.6, float("nan")]), E.EVLB_EINVAL),
+    (dict(nx=[256, 300], T_iso_sys=[0.0, 0.6], adjoint=1), E.EVLB_EUNSUPPORTED),
 ])
 def test_validate_rejects(kw, code):
     base = dict(q=16, dx=0.125, dt=DT16, nx=256)
@@ -132,6 +135,7 @@ def test_validate_accepts_2d_workload():
     (dict(dt=0.2), E.EVLB_ECFL),
     (dict(dt=0.6 * 0.25 / 6.630878198393129), E.EVLB_ECFL),  # 1D limit met, 2D sum exceeded
     (dict(T_iso=float("nan")), E.EVLB_EINVAL),
+    (dict(T_iso_sys=[0.6]), E.EVLB_EUNSUPPORTED),
 ])
 def test_validate_rejects_2d(kw, code):
     p = _p2(**kw)
@@ -154,3 +158,18 @@ def test_init_2d_rejects_missing_workspace_before_device_work():
     assert L.evlb_init(ctypes.byref(p), None, 0, None, ctypes.byref(out)) == E.EVLB_EWORKSPACE
     assert L.evlb_init(ctypes.byref(p), ctypes.c_void_p(256), 16, None, ctypes.byref(out)) == E.EVLB_EWORKSPACE
     assert out.value is None
+
+
+def test_per_system_isothermal_temperatures():
+    """T_iso_sys: accepted with zeros (thermal) and positive entries, also with
+    the adjoint when every entry is 0; one double per node more workspace; one
+    value per system required by the binding."""
+    nxs = [2000, 1500, 1000]
+    base = P.make_params(16, 0.1, 5e-3, nxs)
+    p = P.make_params(16, 0.1, 5e-3, nxs, T_iso_sys=[0.55, 0.0, 0.7])
+    assert P.evlb_validate(p) == E.EVLB_OK
+    grow = P.evlb_workspace_bytes(p) - P.evlb_workspace_bytes(base)
+    assert 8 * sum(nxs) <= grow < 8 * sum(nxs) + 256
+    assert P.evlb_validate(P.make_params(16, 0.1, 5e-3, nxs, adjoint=1, T_iso_sys=[0.0] * 3)) == E.EVLB_OK
+    with pytest.raises(ValueError):
+        P.make_params(16, 0.1, 5e-3, nxs, T_iso_sys=[0.6, 0.6])

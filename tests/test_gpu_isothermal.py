@@ -2,8 +2,9 @@
 
 Parity of the HIP path with the oracle's isothermal mode (1D right-hand
 side per term and 10 steps, 2D right-hand side and one step), and the
-stationary planar interfaces of Sec. III A at the paper's own parameters:
-five temperatures T in {0.55, 0.6, 0.65, 0.7, 0.74}, the domain
+stationary planar interfaces of Sec. III A at the paper's own parameters,
+run as one batch of five systems with a fixed temperature each (T_iso_sys):
+T in {0.55, 0.6, 0.65, 0.7, 0.74}, the domain
 [-100 sigma, 100 sigma] at dx = sigma/10, Q = 16, dt = 5e-3, the tanh
 profile of eq:tanh with x0 = 50 sigma at the Maxwell densities.  After 1e5
 steps (t = 500; the paper runs 1e6) the bulk densities lie on the Maxwell
@@ -97,22 +98,63 @@ TEMPS = (0.55, 0.6, 0.65, 0.7, 0.74)
 STEPS_3A = 100000
 
 
+@pytest.mark.parametrize("tile", [16, 63, 64])
+def test_per_system_isothermal_batch_matches_oracle(tile):
+    """A ragged batch with one fixed temperature per system (one of them
+    thermal): every system after 1 and 10 steps against its own oracle run."""
+    Q, dx, dt = 16, 0.125, 0.2 * 0.125 / 6.630878198393129
+    nxs, temps = [256, 300, 211], [0.55, 0.0, 0.62]
+    parts, tabs = [], []
+    for N, Ti in zip(nxs, temps):
+        x = np.arange(N) / N
+        n = 0.3 * (1 + 0.1 * np.sin(2 * np.pi * x))
+        u = 0.05 * np.sin(4 * np.pi * x)
+        T = 0.6 * (1 + 0.05 * np.cos(2 * np.pi * x))
+        tb = step1d.Tables(Params(Q=Q, dx=dx, dt=dt, T_iso=Ti))
+        parts.append(step1d.initial_state(n, u, T, tb))
+        tabs.append(tb)
+    f0 = np.stack([np.concatenate([p[0] for p in parts], axis=1), np.concatenate([p[1] for p in parts], axis=1)])
+    offs = np.cumsum([0] + nxs)
+    for mode in (1, 2):
+        print(f"per-system T_iso case tile={tile} mode={mode}", flush=True)
+        s = E.Solver(Q, dx, dt, nxs, exec_mode=mode, tile_nodes=tile, T_iso_sys=temps)
+        f = td(f0)
+        s.step(f, 1)
+        got1 = f.cpu().numpy()
+        s.step(f, 9)
+        got10 = f.cpu().numpy()
+        assert s.status() == 0
+        for i, tb in enumerate(tabs):
+            sl = slice(offs[i], offs[i + 1])
+            F1, G1 = step1d.rk3_step(parts[i][0], parts[i][1], tb)
+            assert rel(got1[:, :, sl], [F1, G1]) < 1e-11, (i, temps[i])
+            F10, G10 = step1d.run(F1, G1, tb, 9)
+            assert rel(got10[:, :, sl], [F10, G10]) < 1e-10, (i, temps[i])
+
+
 def test_stationary_interfaces_sec3a_on_maxwell_construction():
     dx, dt, nx, x0 = 0.1, 5e-3, 2000, 50.0
     a = model.attraction_parameter_discrete(Params(Q=16, dx=dx, dt=dt))
     Tc = model.critical_point(a)[1]
     x = workloads.grid(nx, dx)
+    dens, maxwell = [], []
     for T in TEMPS:
         nv, nl = model.maxwell_construction(T, a)
         xi = np.sqrt(3.0 / (4 * np.pi * np.sqrt(3) * (Tc - T)))
-        n = nl + (nv - nl) / 2 * (1 + np.tanh((np.abs(x) - x0) / xi))
-        s = E.Solver(16, dx, dt, nx, T_iso=T)
-        f = s.equilibrium(td(n), td(np.zeros(nx)), td(np.full(nx, T)))
-        for _ in range(4):
-            s.step(f, STEPS_3A // 4)
-        assert s.status() == E.EVLB_OK
-        mom = s.moments(f).cpu().numpy()
-        print(f"T {T}: n_l {mom[0][nx // 2]:.6f} (Maxwell {nl:.6f})  n_v {mom[0][0]:.6f} (Maxwell {nv:.6f})",
-              flush=True)
-        assert abs(mom[0][nx // 2] - nl) < 1e-3, (T, mom[0][nx // 2], nl)
-        assert abs(mom[0][0] - nv) < 1e-3, (T, mom[0][0], nv)
+        dens.append(nl + (nv - nl) / 2 * (1 + np.tanh((np.abs(x) - x0) / xi)))
+        maxwell.append((nv, nl))
+    # the five temperatures as five systems of one batched context
+    k = len(TEMPS)
+    s = E.Solver(16, dx, dt, [nx] * k, T_iso_sys=list(TEMPS))
+    f = s.equilibrium(td(np.concatenate(dens)), td(np.zeros(k * nx)),
+                      td(np.concatenate([np.full(nx, T) for T in TEMPS])))
+    for _ in range(4):
+        s.step(f, STEPS_3A // 4)
+    assert s.status() == E.EVLB_OK
+    n = s.moments(f).cpu().numpy()[0]
+    for i, T in enumerate(TEMPS):
+        nv, nl = maxwell[i]
+        n_l, n_v = n[i * nx + nx // 2], n[i * nx]
+        print(f"T {T}: n_l {n_l:.6f} (Maxwell {nl:.6f})  n_v {n_v:.6f} (Maxwell {nv:.6f})", flush=True)
+        assert abs(n_l - nl) < 1e-3, (T, n_l, nl)
+        assert abs(n_v - nv) < 1e-3, (T, n_v, nv)
