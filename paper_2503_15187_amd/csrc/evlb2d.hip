@@ -15,7 +15,7 @@
 //                  (eq:carnstar), force (antisymmetric cell pairs), transport
 //                  (eq:viscosity, eq:tau, eq:prandtl), 4th-order central
 //                  gradients of X = n^2 chi T, T and u along x and y.
-//   adv_kernel     one wavefront per strip of 58 columns x 64 rows of one
+//   adv_kernel     one wavefront per strip of 58 columns x 128 rows of one
 //                  velocity plane, marching down the rows with register
 //                  rings; every WENO-5 face computed once from per-node
 //                  stencil terms that three faces share,
@@ -294,7 +294,7 @@ __global__ __launch_bounds__(FNT) void fields_kernel(Dev D, const double* __rest
 // three weights by the same 256, which cancels.  The division is a hardware
 // reciprocal refined by two Newton steps r <- r (2 - d r).
 //
-// Lane t holds column x0 - 3 + t and marches down 64 rows.  Along y the
+// Lane t holds column x0 - 3 + t and marches down 128 rows.  Along y the
 // triples of rows y - 1 .. y + 2 and the raw rows y .. y + 3 sit in rings of
 // four registers indexed by row mod 4; the loop is unrolled by four so that
 // every ring index is a constant.  Along x each lane builds the triple of its
@@ -302,7 +302,7 @@ __global__ __launch_bounds__(FNT) void fields_kernel(Dev D, const double* __rest
 // lacks from the lanes that own them; the face on its right comes from lane
 // t + 1.  Lanes 3 .. 60 produce the 58 outputs.  No LDS, no barrier.
 constexpr int AW = 58;   // output columns per wavefront
-constexpr int AR = 64;   // output rows per wavefront (a multiple of 4)
+constexpr int AR = 128;  // output rows per wavefront (a multiple of 4)
 constexpr int ANT = 256; // four strips per workgroup
 
 struct AdvArgs {
