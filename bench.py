@@ -85,6 +85,29 @@ def measured_traffic(workload, kernel):
     return e["bytes_per_launch"]
 
 
+def copy_bandwidth(torch, dev, mib=1024, reps=10):
+    """Context for the roofline: the rate of a plain device-to-device copy of
+    `mib` MiB (read + write bytes over the copy time, HIP events on the
+    current stream), next to the published 8 TB/s peak."""
+    n = mib * 1024 * 1024 // 8
+    x = torch.ones(n, dtype=torch.float64, device=dev)
+    y = torch.empty_like(x)
+    y.copy_(x)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        y.copy_(x)
+    e1.record()
+    torch.cuda.synchronize()
+    s = e0.elapsed_time(e1) / 1e3 / reps
+    gbs = 2 * n * 8 / s / 1e9
+    del x, y
+    return {"GB_per_s": gbs, "frac_of_peak": gbs / HBM_PEAK_GBS, "bytes": 2 * n * 8,
+            "what": f"torch copy_ of {mib} MiB FP64, device to device"}
+
+
 def default_tile(nx, cus=256):
     """The library's automatic tile choice: column tiles when they give at
     least four wavefronts per CU, else narrow 16-node tiles."""
@@ -366,6 +389,7 @@ def main():
         out["secondary"] = out.get("secondary", []) + [adjoint_ratio(E, torch, dev, args.adjoint_steps)]
     if args.paper_runs:
         out["secondary"] = out.get("secondary", []) + paper_runs(E, torch, dev, args.paper_3b_steps)
+    out["hbm_copy"] = copy_bandwidth(torch, dev)
     if args.calibrate_copy:
         x = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device=dev)
         y = torch.empty_like(x)
