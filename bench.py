@@ -30,7 +30,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-BYTES_PER_UPDATE_STEP = 128.0   # per site-velocity per RK3 step (F and G): see the design doc
+# algorithmic HBM bytes per site-velocity per RK3 step (F and G together):
+# stage 1 reads f^n and writes f^(1) (16 + 16 B), stages 2 and 3 each read
+# f^(s-1) and f^n and write f^(s) (48 B); node fields and halo re-reads excluded
+BYTES_PER_UPDATE_STEP = 128.0
 KERNEL_NAMES = {16: "stage_kernel<{q},16,{q}>", 63: "stage_kernel_col<{q}>", 64: "stage_kernel<{q},64,8>"}
 
 
