@@ -118,7 +118,10 @@ def default_tile(nx, cus=256):
     return 63 if sum((v + 62) // 63 for v in nxs) >= 4 * cus else 16
 
 
-def measure(E, torch, dev, q, dx, dt, nx, n, u, T, steps, warmup, mode=None, tile=None):
+def measure(E, torch, dev, q, dx, dt, nx, n, u, T, steps, warmup, mode=None, tile=None, graph=True):
+    """Times `steps` RK3 steps.  Per-stage launches are replayed from a
+    captured HIP graph of up to 500 steps (graph=True) or launched one by
+    one; the persistent mode is one launch either way."""
     from paper_2503_15187_amd import autotune
     td = lambda a: torch.tensor(a, dtype=torch.float64, device=dev)
     n_tot = int(np.sum(nx))
@@ -130,8 +133,15 @@ def measure(E, torch, dev, q, dx, dt, nx, n, u, T, steps, warmup, mode=None, til
     s = E.Solver(q, dx, dt, nx, device=dev, exec_mode=mode, tile_nodes=tile)
     f = s.equilibrium(td(n), td(u), td(T))
     stream = torch.cuda.current_stream()
+    persistent = mode == E.EVLB_EXEC_PERSISTENT
+    use_graph = graph and not persistent
+    if use_graph:
+        g = autotune.GraphStepper(s, f, chunk=max(1, min(steps, 500)))
+        advance = g.step
+    else:
+        advance = lambda k: s.step(f, k)  # noqa: E731
     if warmup:
-        s.step(f, warmup)
+        advance(warmup)
     torch.cuda.synchronize()
     if s.status() != 0:
         raise RuntimeError("non-finite state during warm-up")
@@ -139,7 +149,7 @@ def measure(E, torch, dev, q, dx, dt, nx, n, u, T, steps, warmup, mode=None, til
     ev1 = torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
     ev0.record(stream)
-    s.step(f, steps)
+    advance(steps)
     ev1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -147,7 +157,6 @@ def measure(E, torch, dev, q, dx, dt, nx, n, u, T, steps, warmup, mode=None, til
     if s.status() != 0:
         raise RuntimeError("device status not ok after the timed run")
     updates = n_tot * q * 3 * steps
-    persistent = mode == E.EVLB_EXEC_PERSISTENT
     launches = 1 if persistent else 3 * steps
     kname = KERNEL_NAMES[tile].format(q=q)
     if persistent:
@@ -156,7 +165,7 @@ def measure(E, torch, dev, q, dx, dt, nx, n, u, T, steps, warmup, mode=None, til
     achieved = alg_bytes / (gpu_s / launches) / 1e9
     return {
         "value": updates / gpu_s, "gpu_s": gpu_s, "wall_s": wall, "ms_per_step": gpu_s * 1e3 / steps,
-        "exec": "persistent" if persistent else "per_stage", "tile_nodes": tile,
+        "exec": "persistent" if persistent else ("per_stage_graph" if use_graph else "per_stage"), "tile_nodes": tile,
         "roofline": {"bound": "hbm", "kernel": kname, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "bytes_per_launch": alg_bytes, "avg_launch_us": gpu_s / launches * 1e6},
@@ -330,6 +339,8 @@ def main():
     ap.add_argument("--paper-3b-steps", type=int, default=None, help="shorten the Sec. III B runs (default: 1e6)")
     ap.add_argument("--steps-2d", type=int, default=10)
     ap.add_argument("--adjoint-steps", type=int, default=2000)
+    ap.add_argument("--no-graph", action="store_true",
+                    help="launch per-stage kernels one by one instead of replaying a captured HIP graph")
     ap.add_argument("--no-autotune", action="store_true",
                     help="use the library's default launch shape (one kernel per stage) instead of timing candidates")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -351,7 +362,8 @@ def main():
     mode, tile = args.exec_mode, args.tile
     if args.no_autotune:
         mode, tile = E.EVLB_EXEC_PER_STAGE, default_tile(c["nx"])
-    m = measure(E, torch, dev, c["Q"], c["dx"], c["dt"], c["nx"], n, u, T, steps, args.warmup, mode, tile)
+    m = measure(E, torch, dev, c["Q"], c["dx"], c["dt"], c["nx"], n, u, T, steps, args.warmup, mode, tile,
+                graph=not args.no_graph)
     out = {
         "metric": "site-velocity updates/s per RK stage (FP64)",
         "value": m["value"],
@@ -380,7 +392,7 @@ def main():
         if args.no_autotune:
             bmode, btile = E.EVLB_EXEC_PER_STAGE, default_tile(cb["nx_list"])
         mb = measure(E, torch, dev, cb["Q"], cb["dx"], cb["dt"], cb["nx_list"], nb, ub, Tb,
-                     args.batch_steps, 5, bmode, btile)
+                     args.batch_steps, 5, bmode, btile, graph=not args.no_graph)
         out["secondary"] = [{
             "config": {"workload": "batched_sweep_1d", "n_sys": cb["n_sys"], "n_tot": int(len(nb)), "q": cb["Q"],
                        "dx": cb["dx"], "exec": mb["exec"], "tile_nodes": mb["tile_nodes"]},
