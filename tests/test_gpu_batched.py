@@ -63,6 +63,24 @@ def test_graph_replays_match_eager_steps(tile):
     assert s.status() == 0
 
 
+def test_graph_replays_single_system_slab():
+    """The headline path: one system (no tile descriptors), Q = 24, narrow
+    tiles.  Every replay of a 5-step graph, with eager work and a
+    synchronisation in between, equals five eager steps bit for bit."""
+    c, n, u, T = workloads.slab_1d(nx=1024)
+    s = E.Solver(c["Q"], c["dx"], c["dt"], c["nx"], exec_mode=1, tile_nodes=16)
+    f_eager = s.equilibrium(td(n), td(u), td(T))
+    f_graph = f_eager.clone()
+    g = AT.GraphStepper(s, f_graph, chunk=5)
+    for i in range(4):
+        g.graph.replay()
+        s.step(f_eager, 5)
+        _ = s.moments(f_graph)[0].sum().item()  # eager work between replays
+        torch.cuda.synchronize()
+        assert torch.equal(f_graph, f_eager), i
+    assert s.status() == 0
+
+
 def test_graph_stepper_remainder():
     c, systems, n, u, T = batch(8, 900)
     s = E.Solver(c["Q"], c["dx"], c["dt"], c["nx_list"], exec_mode=1, tile_nodes=16)
