@@ -675,6 +675,15 @@ __device__ void stage_tile_narrow(const DevParams& P, const StageArgs& A, int ti
   __syncthreads();
 
   // ---- 2. contact value, transport, Hermite moments, force sums, faces ----
+  // B operands of this wavefront's Dp chain, read before the faces
+  double bD[KC];
+#pragma unroll
+  for (int b = 0; b < KC; ++b) bD[b] = 0.0;
+  if (dchain) {
+    const int brow = chD / RB == 1 ? Q : 0;
+#pragma unroll
+    for (int b = 0; b < KC; ++b) bD[b] = S.f[brow + 4 * b + (lane >> 4)][(lane & 15) + HF];
+  }
   if (tid < W + 4) {
     // chi(nbar) and X = n^2 chi T on the tile +-2 (eq:carnstar)
     const int c = tid, cn = c + hn - 2;
@@ -738,41 +747,68 @@ __device__ void stage_tile_narrow(const DevParams& P, const StageArgs& A, int ti
     if (m <= m1) s0 += S.cf[m - 1] * (S.n[cn + m] - S.n[cn - m]);
     S.fpart[k][j] = s0 + s1;
   }
-  // faces on the threads without contact-value or Hermite work; with six or
-  // more wavefronts the contact-value wavefront takes none
-  constexpr int WS = NT >= 384 ? 64 : W + 4;
-  if ((P.term_mask & EVLB_TERM_ADV) && tid >= WS && tid < NT - W) {
+  // WENO faces on the threads without contact-value or Hermite work.  With
+  // six or more wavefronts the contact-value wavefront takes none, wavefronts
+  // 1 .. NW-2 take FM faces per thread and the Hermite wavefront's other lanes
+  // the rest, so that no wavefront runs many faces and the recurrence too.
+  // Each face index is clamped into range and only the store is guarded, so
+  // the faces of a thread are independent straight-line code.
+  if (P.term_mask & EVLB_TERM_ADV) {
     constexpr int NFACE = 2 * Q * (W + 1);
-    constexpr int NFT = NT - W - WS;
+    constexpr bool SPLIT = NT >= 384;
+    constexpr int WS = SPLIT ? 64 : W + 4;            // first face thread
+    constexpr int NMAIN = SPLIT ? 64 * (NW - 2) : NT - W - WS;
+    constexpr int FM = SPLIT ? NFACE / NMAIN : (NFACE + NMAIN - 1) / NMAIN;
+    constexpr int NREST = SPLIT ? NFACE - FM * NMAIN : 0;  // faces for the last wavefront
+    static_assert(!SPLIT || NREST <= 64 - W, "the remaining faces fit the last wavefront");
+    int base = -1, nf = 0, stride = 0;
+    if (tid >= WS && tid < WS + NMAIN) {
+      base = tid - WS;
+      nf = FM;
+      stride = NMAIN;
+    } else if (SPLIT && tid >= 64 * (NW - 1) && tid < 64 * (NW - 1) + NREST) {
+      base = FM * NMAIN + tid - 64 * (NW - 1);
+      nf = 1;
+      stride = 0;
+    }
+    // face idx of row r = idx / (W + 1): face i0 + jf - 1/2, upwind by the sign of p_k
+    auto face = [&](int idx, bool keep) {
+      const int r = idx / (W + 1);
+      const int jf = idx - r * (W + 1);
+      const int kr = r < Q ? r : r - Q;
+      const bool pos = kr >= Q / 2;  // p_k > 0: upwind from the left
+      const double* fr = &S.f[r][0];
+      const int b0 = pos ? jf : jf + 5;
+      const int st = pos ? 1 : -1;
+      const double h = weno5(fr[b0], fr[b0 + st], fr[b0 + 2 * st], fr[b0 + 3 * st], fr[b0 + 4 * st], P.weno_eps);
+      if (keep) S.flux[r][jf] = h;
+    };
+    if (nf == FM) {  // whole wavefronts take this branch or the next
 #pragma unroll
-    for (int i = 0; i < (NFACE + NFT - 1) / NFT; ++i) {
-      const int idx = tid - WS + i * NFT;
-      if (idx < NFACE) {
-        const int r = idx / (W + 1);
-        const int jf = idx - r * (W + 1);  // face i0 + jf - 1/2
-        const int kr = r < Q ? r : r - Q;
-        const bool pos = kr >= Q / 2;      // p_k > 0: upwind from the left
-        const double* fr = &S.f[r][0];
-        const int b0 = pos ? jf : jf + 5;
-        const int st = pos ? 1 : -1;
-        S.flux[r][jf] = weno5(fr[b0], fr[b0 + st], fr[b0 + 2 * st], fr[b0 + 3 * st], fr[b0 + 4 * st],
-                              P.weno_eps);
+      for (int i = 0; i < FM; ++i) {
+        const int want = base + i * stride;
+        const bool keep = want < NFACE;
+        face(keep ? want : base, keep);
       }
+    } else if (nf == 1) {
+      face(base, true);
     }
   }
   if (dchain) {
-    // (Dp F) or (Dp G) for one row block on the MFMA
+    // (Dp F) or (Dp G) for one row block on the MFMA, as two independent
+    // accumulation chains (even and odd contraction steps)
     const int p = 1 + chD / RB, rb = chD % RB;
     const int col = lane & 15, c = lane >> 4;
-    const int brow = p == 2 ? Q : 0;
-    dbl4 acc = {0.0, 0.0, 0.0, 0.0};
+    dbl4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int b = 0; b < KC; ++b)
-      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(aD[b], S.f[brow + 4 * b + c][col + HF], acc, 0, 0, 0);
+    for (int b = 0; b < KC; b += 2) {
+      acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(aD[b], bD[b], acc0, 0, 0, 0);
+      if (b + 1 < KC) acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(aD[b + 1], bD[b + 1], acc1, 0, 0, 0);
+    }
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int row = 16 * rb + 4 * r + c;
-      if (row < Q) S.ctr[p][row][col] = acc[r];
+      if (row < Q) S.ctr[p][row][col] = acc0[r] + acc1[r];
     }
   }
   __syncthreads();
