@@ -136,6 +136,79 @@ def test_q8_rhs_and_steps_match_oracle(tile):
         assert s.status() == 0
 
 
+def _smooth_state(N):
+    """Smooth periodic density, velocity and temperature waves on N nodes."""
+    x = np.arange(N) / N
+    n = 0.3 * (1 + 0.1 * np.sin(2 * np.pi * x) + 0.05 * np.cos(6 * np.pi * x))
+    u = 0.04 * np.sin(4 * np.pi * x)
+    T = 0.6 * (1 + 0.05 * np.cos(2 * np.pi * x))
+    return n, u, T
+
+
+# force_model: EV1 = 0 (eq:F1 convolution), EV2 = 1 (eq:F2 local stencil), none = 2
+@pytest.mark.parametrize("tile", [16, 63, 64])
+@pytest.mark.parametrize("force", [1, 2])
+def test_ev2_and_no_force_match_oracle(force, tile):
+    """The EV2 force of eq:F2 and the force-free model (with a uniform
+    external force) on a ragged 300-node grid: right-hand side per term, and
+    1 and 10 steps in both launch modes."""
+    Q, N, dx = 16, 300, 1 / 8
+    dt = 0.2 * dx / 6.630878198393129
+    kw = dict(force_model=force, g_ext=0.02 if force == 2 else 0.0)
+    n, u, T = _smooth_state(N)
+    c = dict(Q=Q, dx=dx, dt=dt)
+    print(f"force case force={force} tile={tile}", flush=True)
+    for mask in (2, 15):
+        tb = oracle_tables(c, term_mask=mask, **kw)
+        F, G = nonequilibrium(*step1d.initial_state(n, u, T, tb), tb)
+        LF, LG = step1d.rhs(F, G, tb)
+        L = solver(c, nx=N, term_mask=mask, tile_nodes=tile, **kw).rhs(td(np.stack([F, G]))).cpu().numpy()
+        assert rel(L, [LF, LG]) < 1e-11, mask
+    tb = oracle_tables(c, **kw)
+    F0, G0 = step1d.initial_state(n, u, T, tb)
+    F1, G1 = step1d.rk3_step(F0, G0, tb)
+    F10, G10 = step1d.run(F1, G1, tb, 9)
+    for mode in (1, 2):
+        s = solver(c, nx=N, exec_mode=mode, tile_nodes=tile, **kw)
+        f = s.equilibrium(td(n), td(u), td(T))
+        s.step(f, 1)
+        assert rel(f.cpu().numpy(), [F1, G1]) < 1e-11, mode
+        s.step(f, 9)
+        assert rel(f.cpu().numpy(), [F10, G10]) < 1e-10, mode
+        assert s.status() == 0
+
+
+@pytest.mark.parametrize("tile", [16, 63, 64])
+@pytest.mark.parametrize("force", [0, 1])
+def test_widest_windows_match_oracle(force, tile):
+    """The widest windows the kernels are built for: sigma/dx = 16 (the
+    averaging window of eq:nbar, 33 nodes) and, for EV1, r_cut/dx = 64 (the
+    force window of eq:F1, 129 nodes) at dx = sigma/16 with r_cut = 4 sigma,
+    on a ragged 300-node grid: right-hand side and 1 and 10 steps."""
+    Q, N, dx = 16, 300, 1 / 16
+    dt = 0.2 * dx / 6.630878198393129
+    kw = dict(force_model=force, r_cut=4.0)
+    n, u, T = _smooth_state(N)
+    c = dict(Q=Q, dx=dx, dt=dt)
+    print(f"window case force={force} tile={tile}", flush=True)
+    tb = oracle_tables(c, **kw)
+    F, G = nonequilibrium(*step1d.initial_state(n, u, T, tb), tb)
+    LF, LG = step1d.rhs(F, G, tb)
+    L = solver(c, nx=N, tile_nodes=tile, **kw).rhs(td(np.stack([F, G]))).cpu().numpy()
+    assert rel(L, [LF, LG]) < 1e-11
+    F0, G0 = step1d.initial_state(n, u, T, tb)
+    F1, G1 = step1d.rk3_step(F0, G0, tb)
+    F10, G10 = step1d.run(F1, G1, tb, 9)
+    for mode in (1, 2):
+        s = solver(c, nx=N, exec_mode=mode, tile_nodes=tile, **kw)
+        f = s.equilibrium(td(n), td(u), td(T))
+        s.step(f, 1)
+        assert rel(f.cpu().numpy(), [F1, G1]) < 1e-11, mode
+        s.step(f, 9)
+        assert rel(f.cpu().numpy(), [F10, G10]) < 1e-10, mode
+        assert s.status() == 0
+
+
 def test_phase_separation_1000_steps_match_oracle():
     """Full phase-separation workload: 256 nodes, Q = 16, 1000 steps."""
     c, n, u, T = case_phase()
