@@ -209,6 +209,45 @@ def test_widest_windows_match_oracle(force, tile):
         assert s.status() == 0
 
 
+@pytest.mark.parametrize("tile", [16, 63, 64])
+def test_tiny_systems_batch_matches_oracle(tile):
+    """Systems shorter than the force window (r_cut/dx = 40 nodes each way):
+    the smallest accepted length (8) and a few others, in one ragged batch,
+    so that the density window and the WENO halo wrap round their periodic
+    system several times.  1 and 10 steps, both launch modes, against
+    independent oracle runs."""
+    Q, dx = 16, 1 / 8
+    dt = 0.2 * dx / 6.630878198393129
+    nxs = [8, 9, 13, 31, 64, 65, 130]
+    c = dict(Q=Q, dx=dx, dt=dt)
+    tb = oracle_tables(c)
+    parts, refs = [], []
+    for i, N in enumerate(nxs):
+        x = np.arange(N) / N
+        n = 0.3 * (1 + 0.05 * np.sin(2 * np.pi * x + i))
+        u = 0.03 * np.cos(2 * np.pi * x)
+        T = 0.6 + 0.02 * np.sin(2 * np.pi * x)
+        parts.append((n, u, T))
+        F, G = step1d.initial_state(n, u, T, tb)
+        F1, G1 = step1d.rk3_step(F, G, tb)
+        refs.append(((F1, G1), step1d.run(F1, G1, tb, 9)))
+    cat = [np.concatenate([p[k] for p in parts]) for k in range(3)]
+    offs = np.cumsum([0] + nxs)
+    print(f"tiny systems tile={tile}", flush=True)
+    for mode in (1, 2):
+        s = solver(c, nx=nxs, exec_mode=mode, tile_nodes=tile)
+        f = s.equilibrium(*[td(a) for a in cat])
+        s.step(f, 1)
+        got1 = f.cpu().numpy()
+        s.step(f, 9)
+        got10 = f.cpu().numpy()
+        assert s.status() == 0
+        for i in range(len(nxs)):
+            sl = slice(offs[i], offs[i + 1])
+            assert rel(got1[:, :, sl], refs[i][0]) < 1e-11, (mode, nxs[i])
+            assert rel(got10[:, :, sl], refs[i][1]) < 1e-10, (mode, nxs[i])
+
+
 def test_phase_separation_1000_steps_match_oracle():
     """Full phase-separation workload: 256 nodes, Q = 16, 1000 steps."""
     c, n, u, T = case_phase()
