@@ -89,27 +89,54 @@ struct StageArgs {
 // Classical WENO-5 (Jiang & Shu) face value from the five upwind-ordered
 // values v0..v4 = f_{i-2}..f_{i+2}; alpha_r = d_r/(eps+beta_r)^2 combined
 // over a common denominator (one reciprocal).
+//
+// Two arithmetic forms of the same function.  LEAN takes common factors out
+// where they cancel -- the candidates are formed as 6 q_r, the smoothness
+// indicators as 12 beta_r against 12 eps, the linear weights as
+// 10 d_r = (1, 6, 3), and 1/6 is applied once beside the reciprocal -- for
+// about ten fewer operations per face: the column and wide tiles, whose
+// faces are throughput work, use it.  The narrow tile's faces sit on its
+// critical path, and there the textbook form measures slightly faster.
+template <bool LEAN>
 __device__ __forceinline__ double weno5(double v0, double v1, double v2, double v3, double v4,
                                         double eps) {
-  const double q0 = (2.0 * v0 - 7.0 * v1 + 11.0 * v2) * (1.0 / 6.0);
-  const double q1 = (-v1 + 5.0 * v2 + 2.0 * v3) * (1.0 / 6.0);
-  const double q2 = (2.0 * v2 + 5.0 * v3 - v4) * (1.0 / 6.0);
   const double c0 = v0 - 2.0 * v1 + v2, e0 = v0 - 4.0 * v1 + 3.0 * v2;
   const double c1 = v1 - 2.0 * v2 + v3, e1 = v1 - v3;
   const double c2 = v2 - 2.0 * v3 + v4, e2 = 3.0 * v2 - 4.0 * v3 + v4;
-  const double b0 = (13.0 / 12.0) * c0 * c0 + 0.25 * e0 * e0;
-  const double b1 = (13.0 / 12.0) * c1 * c1 + 0.25 * e1 * e1;
-  const double b2 = (13.0 / 12.0) * c2 * c2 + 0.25 * e2 * e2;
-  double t0 = eps + b0; t0 *= t0;
-  double t1 = eps + b1; t1 *= t1;
-  double t2 = eps + b2; t2 *= t2;
-  const double w0 = 0.1 * t1 * t2, w1 = 0.6 * t0 * t2, w2 = 0.3 * t0 * t1;
+  double q0, q1, q2, w0, w1, w2;
+  if constexpr (LEAN) {
+    q0 = 2.0 * v0 - 7.0 * v1 + 11.0 * v2;
+    q1 = -v1 + 5.0 * v2 + 2.0 * v3;
+    q2 = 2.0 * v2 + 5.0 * v3 - v4;
+    const double eps12 = 12.0 * eps;
+    double t0 = fma(13.0 * c0, c0, fma(3.0 * e0, e0, eps12)); t0 *= t0;
+    double t1 = fma(13.0 * c1, c1, fma(3.0 * e1, e1, eps12)); t1 *= t1;
+    double t2 = fma(13.0 * c2, c2, fma(3.0 * e2, e2, eps12)); t2 *= t2;
+    w0 = t1 * t2;
+    w1 = 6.0 * t0 * t2;
+    w2 = 3.0 * t0 * t1;
+  } else {
+    q0 = (2.0 * v0 - 7.0 * v1 + 11.0 * v2) * (1.0 / 6.0);
+    q1 = (-v1 + 5.0 * v2 + 2.0 * v3) * (1.0 / 6.0);
+    q2 = (2.0 * v2 + 5.0 * v3 - v4) * (1.0 / 6.0);
+    const double b0 = (13.0 / 12.0) * c0 * c0 + 0.25 * e0 * e0;
+    const double b1 = (13.0 / 12.0) * c1 * c1 + 0.25 * e1 * e1;
+    const double b2 = (13.0 / 12.0) * c2 * c2 + 0.25 * e2 * e2;
+    double t0 = eps + b0; t0 *= t0;
+    double t1 = eps + b1; t1 *= t1;
+    double t2 = eps + b2; t2 *= t2;
+    w0 = 0.1 * t1 * t2;
+    w1 = 0.6 * t0 * t2;
+    w2 = 0.3 * t0 * t1;
+  }
   // divide through the hardware reciprocal and two Newton steps r <- r (2 - d r)
   const double den = w0 + w1 + w2;
   double r = __builtin_amdgcn_rcp(den);
   r = fma(r, fma(-den, r, 1.0), r);
   r = fma(r, fma(-den, r, 1.0), r);
-  return (w0 * q0 + w1 * q1 + w2 * q2) * r;
+  double num = w0 * q0 + w1 * q1 + w2 * q2;
+  if constexpr (LEAN) num *= 1.0 / 6.0;
+  return num * r;
 }
 
 // Launch shape of the wide stage kernel: tiles of W = 64 nodes, NG groups of
@@ -328,7 +355,7 @@ __device__ void stage_tile(const DevParams& P, const StageArgs& A, int tile, Sme
         const double* fr = &S.f[r][0];
         const int b0 = pos ? jf : jf + 5;
         const int st = pos ? 1 : -1;
-        S.flux[r][jf] = weno5(fr[b0], fr[b0 + st], fr[b0 + 2 * st], fr[b0 + 3 * st], fr[b0 + 4 * st],
+        S.flux[r][jf] = weno5<true>(fr[b0], fr[b0 + st], fr[b0 + 2 * st], fr[b0 + 3 * st], fr[b0 + 4 * st],
                               P.weno_eps);
       }
     }
@@ -780,7 +807,7 @@ __device__ void stage_tile_narrow(const DevParams& P, const StageArgs& A, int ti
       const double* fr = &S.f[r][0];
       const int b0 = pos ? jf : jf + 5;
       const int st = pos ? 1 : -1;
-      const double h = weno5(fr[b0], fr[b0 + st], fr[b0 + 2 * st], fr[b0 + 3 * st], fr[b0 + 4 * st], P.weno_eps);
+      const double h = weno5<false>(fr[b0], fr[b0 + st], fr[b0 + 2 * st], fr[b0 + 3 * st], fr[b0 + 4 * st], P.weno_eps);
       if (keep) S.flux[r][jf] = h;
     };
     if (nf == FM) {  // whole wavefronts take this branch or the next
@@ -1179,8 +1206,8 @@ __device__ void stage_tile_col(const DevParams& P, const StageArgs& A, int tile,
       const int st = pos ? 1 : -1;
       const double* fr = &S.f[k][0];
       const double* gr = &S.f[Q + k][0];
-      const double hF = weno5(fr[b0], fr[b0 + st], fr[b0 + 2 * st], fr[b0 + 3 * st], fr[b0 + 4 * st], P.weno_eps);
-      const double hG = weno5(gr[b0], gr[b0 + st], gr[b0 + 2 * st], gr[b0 + 3 * st], gr[b0 + 4 * st], P.weno_eps);
+      const double hF = weno5<true>(fr[b0], fr[b0 + st], fr[b0 + 2 * st], fr[b0 + 3 * st], fr[b0 + 4 * st], P.weno_eps);
+      const double hG = weno5<true>(gr[b0], gr[b0 + st], gr[b0 + 2 * st], gr[b0 + 3 * st], gr[b0 + 4 * st], P.weno_eps);
       const double hFr = __shfl_down(hF, 1);
       const double hGr = __shfl_down(hG, 1);
       LF = -pk * (hFr - hF) * P.inv_dx;
