@@ -86,6 +86,15 @@ struct StageArgs {
   int rhs_mode;          // write L(f_prev) instead of a stage
 };
 
+// 1/x from the hardware reciprocal and two Newton steps r <- r (2 - x r):
+// within an ulp or two of the quotient, with a shorter dependency chain
+// than the correctly rounded division
+__device__ __forceinline__ double rcpn(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(r, fma(-x, r, 1.0), r);
+  return fma(r, fma(-x, r, 1.0), r);
+}
+
 // Classical WENO-5 (Jiang & Shu) face value from the five upwind-ordered
 // values v0..v4 = f_{i-2}..f_{i+2}; alpha_r = d_r/(eps+beta_r)^2 combined
 // over a common denominator (one reciprocal).
@@ -1121,7 +1130,7 @@ __device__ void stage_tile_col(const DevParams& P, const StageArgs& A, int tile,
     if (jj <= P.ms) s0 += S.sav[jj + P.ms] * S.n[cn + jj];
     const double eta = P.eta_c * (s0 + s1);
     const double om = 1.0 - eta;
-    const double chi = (2.0 - eta) / (2.0 * om * om * om);
+    const double chi = (2.0 - eta) * rcpn(2.0 * om * om * om);
     const double nn = S.n[cn];
     S.chi[c] = chi;
     S.X[c] = nn * nn * chi * S.T[c];
@@ -1151,20 +1160,20 @@ __device__ void stage_tile_col(const DevParams& P, const StageArgs& A, int tile,
                       (0.5 * P.inv_dx * P.inv_dx * P.inv_dx);
     Fx += P.two_a * d1 + P.kappa * d3;
   }
-  const double Ag = (S.X[c - 2] - 8.0 * S.X[c - 1] + 8.0 * S.X[c + 1] - S.X[c + 2]) * idx12 / S.X[c];
-  const double Bg = (S.T[c - 2] - 8.0 * S.T[c - 1] + 8.0 * S.T[c + 1] - S.T[c + 2]) * idx12 / T;
+  const double invT = rcpn(T);
+  const double Ag = (S.X[c - 2] - 8.0 * S.X[c - 1] + 8.0 * S.X[c + 1] - S.X[c + 2]) * idx12 * rcpn(S.X[c]);
+  const double Bg = (S.T[c - 2] - 8.0 * S.T[c - 1] + 8.0 * S.T[c + 1] - S.T[c + 2]) * idx12 * invT;
   const double Ug = (S.u[c - 2] - 8.0 * S.u[c - 1] + 8.0 * S.u[c + 1] - S.u[c + 2]) * idx12;
   const double bn = P.b * n;
   const double y = bn * chi;
   const double c12 = 0.16 * (1.0 + 12.0 / M_PI);
   const double c32 = 0.36 * (1.0 + 32.0 / (9.0 * M_PI));
-  const double mu = P.mu0c * sqrt(T) * (1.0 / chi + 0.8 * bn + c12 * bn * bn * chi);
-  const double nu = chi * n * T * (1.0 + 0.4 * y) / mu;
-  const double Pr = (2.0 / 3.0) * (1.0 + 0.6 * y) * (1.0 + 0.8 * y + c12 * y * y) /
-                    ((1.0 + 0.4 * y) * (1.0 + 1.2 * y + c32 * y * y));
-  const double sS = (1.0 - Pr) * qj / (5.0 * n * T * T);
+  const double mu = P.mu0c * sqrt(T) * (rcpn(chi) + 0.8 * bn + c12 * bn * bn * chi);
+  const double nu = chi * n * T * (1.0 + 0.4 * y) * rcpn(mu);
+  const double Pr = (2.0 / 3.0) * (1.0 + 0.6 * y) * (1.0 + 0.8 * y + c12 * y * y) *
+                    rcpn((1.0 + 0.4 * y) * (1.0 + 1.2 * y + c32 * y * y));
+  const double sS = (1.0 - Pr) * qj * (0.2 * invT * invT) * rcpn(n);
   const double pre = -bn * chi;
-  const double invT = 1.0 / T;
   // Hermite moments a_0 = n, a_1 = n u, a_{l+1} = u a_l + l (T - 1) a_{l-1}
   double a[Q];
   a[0] = n;
