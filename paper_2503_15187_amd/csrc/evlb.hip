@@ -734,7 +734,7 @@ __device__ void stage_tile_narrow(const DevParams& P, const StageArgs& A, int ti
     for (; jj <= P.ms; ++jj) s0 += S.sav[jj + P.ms] * S.n[cn + jj];
     const double eta = P.eta_c * ((s0 + s1) + (s2 + s3));
     const double om = 1.0 - eta;
-    const double chi = (2.0 - eta) / (2.0 * om * om * om);
+    const double chi = (2.0 - eta) * rcpn(2.0 * om * om * om);
     const double nn = S.n[cn];
     S.chi[c] = chi;
     S.X[c] = nn * nn * chi * Tv;
@@ -745,11 +745,12 @@ __device__ void stage_tile_narrow(const DevParams& P, const StageArgs& A, int ti
       const double mu0 = P.mu0c * sqrt(Tv);
       const double c12 = 0.16 * (1.0 + 12.0 / M_PI);
       const double c32 = 0.36 * (1.0 + 32.0 / (9.0 * M_PI));
-      const double mu = mu0 * (1.0 / chi + 0.8 * bn + c12 * bn * bn * chi);
-      S.nf[NF_NU][c - 2] = chi * nn * Tv * (1.0 + 0.4 * y) / mu;
-      const double Pr = (2.0 / 3.0) * (1.0 + 0.6 * y) * (1.0 + 0.8 * y + c12 * y * y) /
-                        ((1.0 + 0.4 * y) * (1.0 + 1.2 * y + c32 * y * y));
-      S.nf[NF_S][c - 2] = (1.0 - Pr) * qv / (5.0 * nn * Tv * Tv);
+      const double mu = mu0 * (rcpn(chi) + 0.8 * bn + c12 * bn * bn * chi);
+      S.nf[NF_NU][c - 2] = chi * nn * Tv * (1.0 + 0.4 * y) * rcpn(mu);
+      const double Pr = (2.0 / 3.0) * (1.0 + 0.6 * y) * (1.0 + 0.8 * y + c12 * y * y) *
+                        rcpn((1.0 + 0.4 * y) * (1.0 + 1.2 * y + c32 * y * y));
+      const double iT = rcpn(Tv);
+      S.nf[NF_S][c - 2] = (1.0 - Pr) * qv * (0.2 * iT * iT) * rcpn(nn);
       S.nf[NF_PRE][c - 2] = -bn * chi;
     }
   }
@@ -869,8 +870,8 @@ __device__ void stage_tile_narrow(const DevParams& P, const StageArgs& A, int ti
       Fx += P.two_a * d1 + P.kappa * d3;
     }
     const double T = S.T[c];
-    S.nf[NF_A][j] = (S.X[c - 2] - 8.0 * S.X[c - 1] + 8.0 * S.X[c + 1] - S.X[c + 2]) * idx12 / S.X[c];
-    S.nf[NF_B][j] = (S.T[c - 2] - 8.0 * S.T[c - 1] + 8.0 * S.T[c + 1] - S.T[c + 2]) * idx12 / T;
+    S.nf[NF_A][j] = (S.X[c - 2] - 8.0 * S.X[c - 1] + 8.0 * S.X[c + 1] - S.X[c + 2]) * idx12 * rcpn(S.X[c]);
+    S.nf[NF_B][j] = (S.T[c - 2] - 8.0 * S.T[c - 1] + 8.0 * S.T[c + 1] - S.T[c + 2]) * idx12 * rcpn(T);
     S.nf[NF_U1][j] = (S.u[c - 2] - 8.0 * S.u[c - 1] + 8.0 * S.u[c + 1] - S.u[c + 2]) * idx12;
     S.nf[NF_FX][j] = Fx;
     S.nf[NF_N][j] = S.n[cn];
@@ -898,7 +899,7 @@ __device__ void stage_tile_narrow(const DevParams& P, const StageArgs& A, int ti
     const double nu = S.nf[NF_NU][j], sS = S.nf[NF_S][j], pre = S.nf[NF_PRE][j];
     const double Ag = S.nf[NF_A][j], Bg = S.nf[NF_B][j], Ug = S.nf[NF_U1][j];
     const double Fx = S.nf[NF_FX][j];
-    const double invT = 1.0 / T;
+    const double invT = rcpn(T);
     const double E = S.ctr[0][k][j];
     const double F = S.f[k][j + HF];
     const double G = S.f[Q + k][j + HF];
