@@ -974,8 +974,9 @@ __device__ void stage_tile_narrow(const DevParams& P, const StageArgs& A, int ti
       ms[m] = s0 + s1;
     }
     const double n = ms[0];
-    const double u = ms[1] / n;
-    const double T = (2.0 / 3.0) * (0.5 * ms[2] + ms[4] - 0.5 * n * u * u) / n;
+    const double in = rcpn(n);
+    const double u = ms[1] * in;
+    const double T = (2.0 / 3.0) * (0.5 * ms[2] + ms[4] - 0.5 * n * u * u) * in;
     const double x3 = ms[3] - 3.0 * u * ms[2] + 3.0 * u * u * ms[1] - u * u * u * n;
     const double q = 0.5 * x3 + ms[5] - u * ms[4];
     A.mom_out[gnode] = n;
@@ -1279,8 +1280,9 @@ __device__ void stage_tile_col(const DevParams& P, const StageArgs& A, int tile,
   // ---- 5. moments of the new state ----------------------------------------
   if (!A.rhs_mode && valid) {
     const double n1 = pm[0];
-    const double u1 = pm[1] / n1;
-    const double T1 = (2.0 / 3.0) * (0.5 * pm[2] + pm[4] - 0.5 * n1 * u1 * u1) / n1;
+    const double in1 = rcpn(n1);
+    const double u1 = pm[1] * in1;
+    const double T1 = (2.0 / 3.0) * (0.5 * pm[2] + pm[4] - 0.5 * n1 * u1 * u1) * in1;
     const double x3 = pm[3] - 3.0 * u1 * pm[2] + 3.0 * u1 * u1 * pm[1] - u1 * u1 * u1 * n1;
     const double q1 = 0.5 * x3 + pm[5] - u1 * pm[4];
     A.mom_out[gnode] = n1;
