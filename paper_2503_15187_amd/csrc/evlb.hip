@@ -1051,16 +1051,33 @@ __device__ void stage_tile_col(const DevParams& P, const StageArgs& A, int tile,
       Fc[k] = A.f_prev[(long long)k * ntot + gown];
       Gc[k] = A.f_prev[(long long)(Q + k) * ntot + gown];
     }
+    // halo columns 0, 1, 2 (nodes -3..-1) and 67, 68 (nodes 64, 65) of all
+    // 2Q rows, spread over the lanes: a few loads per lane instead of 2Q on
+    // five lanes
+    constexpr int NH = 5 * 2 * Q, LH = (NH + 63) / 64;
+    double hv[LH];
+#pragma unroll
+    for (int i = 0; i < LH; ++i) {
+      const int idx = lane + 64 * i;
+      hv[i] = 0.0;
+      if (idx < NH) {
+        const int r = idx / 5, h = idx - 5 * r;
+        const int c = h < 3 ? h : h + 64;
+        hv[i] = A.f_prev[(long long)r * ntot + off + wrapi(i0 - HF + c, nsys)];
+      }
+    }
 #pragma unroll
     for (int k = 0; k < Q; ++k) {
       S.f[k][lane + HF] = Fc[k];
       S.f[Q + k][lane + HF] = Gc[k];
     }
-    if (lane < 5) {  // columns 0, 1, 2 (nodes -3..-1) and 67, 68 (nodes 64, 65)
-      const int c = lane < 3 ? lane : lane + 64;
-      const long long gh = off + wrapi(i0 - HF + c, nsys);
 #pragma unroll
-      for (int r = 0; r < 2 * Q; ++r) S.f[r][c] = A.f_prev[(long long)r * ntot + gh];
+    for (int i = 0; i < LH; ++i) {
+      const int idx = lane + 64 * i;
+      if (idx < NH) {
+        const int r = idx / 5, h = idx - 5 * r;
+        S.f[r][h < 3 ? h : h + 64] = hv[i];
+      }
     }
   }
   // density window, u and T on nodes -2..64, the averaging and force tables:
