@@ -547,7 +547,7 @@ template <bool FRC>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void vel_kernel(Dev D, VelArgs A, const double* __restrict__ vel,
                                                   const double* __restrict__ meq,
                                                   const double* __restrict__ dpm) {
-  __shared__ double s_ey[4][16][Q];  // per wave: e_l(u_y) of its 16 nodes
+  __shared__ double s_ey[4][Q][16];  // per wave: e_l(u_y) of its 16 nodes (node fastest: no bank conflicts)
   __shared__ double s_pc[4][4][4][64];  // per wave: row polynomial coefficients [al be ga ne][j][lane]
   __shared__ double s_aop[4][64];       // MFMA A operands Dp[nd][g + 4 b] (the same for every wave)
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -574,7 +574,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
       double s = 0.0;
 #pragma unroll
       for (int m = 0; m < Q; ++m) s += meq[(g + 4 * i) * Q + m] * a[m];
-      s_ey[wave][nd][g + 4 * i] = s;
+      s_ey[wave][g + 4 * i][nd] = s;
     }
     hermite_coeffs(ux, T, a);
 #pragma unroll
@@ -592,7 +592,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     if (wave == 0) s_aop[j][lane] = dpm[nd * Q + g + 4 * j];
   }
   __syncthreads();
-  const double* eyv = &s_ey[wave][nd][0];
+  const double* eyv = &s_ey[wave][0][nd];  // e_l at eyv[16 l]
 
   // per-lane byte offset of (row g, node) from a plane base; < 2^31 by the
   // node-count limit of the 2D path
@@ -688,7 +688,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
       }
       const double pl = vl[l];
       const double xy = pl - uy;
-      const double eyl = eyv[l];
+      const double eyl = eyv[16 * l];
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         double R = pc[3][j][pli] * eyl * (pc[0][j][pli] + xy * (pc[1][j][pli] + xy * (pc[2][j][pli] + de * xy))) -
