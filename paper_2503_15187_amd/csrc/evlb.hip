@@ -989,6 +989,17 @@ __device__ void stage_tile_narrow(const DevParams& P, const StageArgs& A, int ti
   __syncthreads();
 }
 
+// Workgroups go to the eight XCDs in turn (workgroup b to XCD b mod 8), and
+// each XCD has its own L2.  xcd_tile gives XCD x the contiguous tiles
+// x q + min(x, r) + i (ntiles = 8 q + r), so that tiles sharing halo and
+// window lines, and a tile's own lines from one stage to the next, meet in
+// one L2.  It is a bijection of 0 .. ntiles - 1.
+__device__ __forceinline__ int xcd_tile(int b, int ntiles) {
+  const int q = ntiles >> 3, r = ntiles & 7;
+  const int x = b & 7, i = b >> 3;
+  return x * q + min(x, r) + i;
+}
+
 template <int Q, int W, int NG>
 __global__ __launch_bounds__(W * NG) void stage_kernel(DevParams P, StageArgs A) {
   if constexpr (W == WN) {
@@ -1003,7 +1014,7 @@ __global__ __launch_bounds__(W * NG) void stage_kernel(DevParams P, StageArgs A)
                  "s"(P.two_a), "s"(P.kappa), "s"(P.T_iso), "s"(P.tiso));
     asm volatile("" ::"s"(A.f_prev), "s"(A.f_n), "s"(A.f_out), "s"(A.mom_in), "s"(A.mom_out), "s"(A.alpha),
                  "s"(A.beta), "s"(A.first), "s"(A.rhs_mode));
-    for (int t = blockIdx.x; t < P.ntiles; t += gridDim.x) stage_tile_narrow<Q>(P, A, t, S);
+    for (int b = blockIdx.x; b < P.ntiles; b += gridDim.x) stage_tile_narrow<Q>(P, A, xcd_tile(b, P.ntiles), S);
   } else {
     __shared__ Smem<Q, W, NG> S;
     load_tables<Q, W, NG>(P, S);
@@ -1317,7 +1328,7 @@ __global__ __launch_bounds__(64) void stage_kernel_col(DevParams P, StageArgs A,
                                                        const double* __restrict__ meq,
                                                        const double* __restrict__ dpm) {
   __shared__ SmemCol<Q> S;
-  for (int t = blockIdx.x; t < P.ntiles; t += gridDim.x) stage_tile_col<Q>(P, A, t, S, vel, meq, dpm);
+  for (int b = blockIdx.x; b < P.ntiles; b += gridDim.x) stage_tile_col<Q>(P, A, xcd_tile(b, P.ntiles), S, vel, meq, dpm);
 }
 
 // Grid-wide barrier for the persistent kernel (all workgroups co-resident:
