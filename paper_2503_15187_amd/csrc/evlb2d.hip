@@ -37,6 +37,16 @@
 namespace evlb2d {
 namespace {
 
+// Workgroups go to the eight XCDs in turn (workgroup b to XCD b mod 8), and
+// each XCD has its own L2.  xcd_block gives XCD x the contiguous blocks
+// x q + min(x, r) + i (nb = 8 q + r), so that neighbouring tiles, which share
+// halo lines, run on one XCD.  A bijection of 0 .. nb - 1.
+__device__ __forceinline__ unsigned xcd_block(unsigned b, unsigned nb) {
+  const unsigned q = nb >> 3, r = nb & 7u;
+  const unsigned x = b & 7u, i = b >> 3;
+  return x * q + (x < r ? x : r) + i;
+}
+
 constexpr int Q = 16;
 constexpr int V = Q * Q;
 constexpr int HMAX = 24;  // max halo of the fields tile (force radius / averaging disc + 2)
@@ -190,7 +200,10 @@ __global__ __launch_bounds__(FNT) void fields_kernel(Dev D, const double* __rest
   double* suy = sux + GX * GY;
   double* sC = suy + GX * GY;
   const int tid = threadIdx.x;
-  const int x0 = blockIdx.x * FTX, y0 = blockIdx.y * FTY;
+  // contiguous ranges of tiles per XCD (row-major over the tile grid): the
+  // density halos of neighbouring tiles meet in one L2
+  const unsigned tb = xcd_block(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x * gridDim.y);
+  const int x0 = (int)(tb % gridDim.x) * FTX, y0 = (int)(tb / gridDim.x) * FTY;
   const long long N = D.ntot;
   for (int i = tid; i < PX * PY; i += FNT) {
     const int r = i / PX, c = i - r * PX;
@@ -440,11 +453,8 @@ __device__ __forceinline__ void adv_strip(AdvStrip& S, const AdvArgs& A) {
 
 __global__ __launch_bounds__(ANT) void adv_kernel(Dev D, AdvArgs A, const double* __restrict__ vel) {
   const int nsx = (D.nx + AW - 1) / AW, nsy = (D.ny + AR - 1) / AR;
-  // consecutive workgroups go to different XCDs; hand each XCD a contiguous
-  // range of strips so that neighbouring strips share its L2
-  unsigned b = blockIdx.x;
-  const unsigned nb = gridDim.x;
-  if ((nb & 7u) == 0) b = (b & 7u) * (nb >> 3) + (b >> 3);
+  // contiguous ranges of strips per XCD: neighbouring strips share its L2
+  const unsigned b = xcd_block(blockIdx.x, gridDim.x);
   const unsigned wave = (unsigned)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const unsigned strip = b * 4u + wave;
   const unsigned per_plane = (unsigned)nsx * (unsigned)nsy;
