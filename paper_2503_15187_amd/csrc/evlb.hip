@@ -1032,11 +1032,18 @@ __global__ __launch_bounds__(W * NG) void stage_kernel(DevParams P, StageArgs A)
 // ---------------------------------------------------------------------------
 constexpr int WC = 63;
 
+// The density window is dead once the contact values and the forces are
+// formed, and u, T and X of nodes -2..64 take its place: the tile then fits
+// eight workgroups per CU (Q = 16).
 template <int Q>
 struct SmemCol {
-  double f[2 * Q][WC + 2 * HF + 1];  // columns: node i0 - 3 + c, c = 0..68
-  double n[WC + 2 * HN_MAX];
-  double u[WC + 4], T[WC + 4], X[WC + 4], chi[WC + 4];
+  double f[2 * Q][WC + 2 * HF];      // columns: node i0 - 3 + c, c = 0..68
+  union {
+    double n[WC + 2 * HN_MAX];
+    struct {
+      double u[WC + 4], T[WC + 4], X[WC + 4];
+    } g;
+  } w;
   double sav[2 * MS_MAX + 1];        // averaging weights
   double cf[MF_MAX];                 // EV1 force taps
 };
@@ -1096,6 +1103,7 @@ __device__ void stage_tile_col(const DevParams& P, const StageArgs& A, int tile,
   const double* mn = A.mom_in;
   constexpr int LN = (WC + 2 * HN_MAX + 63) / 64;
   constexpr int LU = (WC + 4 + 63) / 64;
+  static_assert(LU == 2, "nodes -2..64 on one or two values per lane");
   constexpr int NSAV = 2 * MS_MAX + 1;
   constexpr int LT = (NSAV + MF_MAX + 63) / 64;
   const int nwin = WC + 2 * hn;
@@ -1130,15 +1138,7 @@ __device__ void stage_tile_col(const DevParams& P, const StageArgs& A, int tile,
 #pragma unroll
   for (int i = 0; i < LN; ++i) {
     const int c = lane + 64 * i;
-    if (c < nwin) S.n[c] = nv[i];
-  }
-#pragma unroll
-  for (int i = 0; i < LU; ++i) {
-    const int c = lane + 64 * i;
-    if (c < WC + 4) {
-      S.u[c] = uv[i];
-      S.T[c] = Tv[i];
-    }
+    if (c < nwin) S.w.n[c] = nv[i];
   }
 #pragma unroll
   for (int i = 0; i < LT; ++i) {
@@ -1148,52 +1148,77 @@ __device__ void stage_tile_col(const DevParams& P, const StageArgs& A, int tile,
   }
   __syncthreads();
 
-  // ---- 2. contact value and X = n^2 chi T on nodes -2..64 ---------------
-  for (int c = lane; c < WC + 4; c += 64) {
-    const int cn = c + hn - 2;
-    double s0 = 0.0, s1 = 0.0;
-    int jj = -P.ms;
-    for (; jj + 1 <= P.ms; jj += 2) {
-      s0 += S.sav[jj + P.ms] * S.n[cn + jj];
-      s1 += S.sav[jj + 1 + P.ms] * S.n[cn + jj + 1];
+  // ---- 2. contact value and X = n^2 chi T on nodes -2..64 (c = lane, and
+  // c = lane + 64 on lanes 0..2), kept in registers ------------------------
+  double chv[LU], Xv[LU];
+#pragma unroll
+  for (int i = 0; i < LU; ++i) {
+    const int cc = lane + 64 * i;
+    chv[i] = 1.0;
+    Xv[i] = 1.0;
+    if (cc < WC + 4) {
+      const int cn = cc + hn - 2;
+      double s0 = 0.0, s1 = 0.0;
+      int jj = -P.ms;
+      for (; jj + 1 <= P.ms; jj += 2) {
+        s0 += S.sav[jj + P.ms] * S.w.n[cn + jj];
+        s1 += S.sav[jj + 1 + P.ms] * S.w.n[cn + jj + 1];
+      }
+      if (jj <= P.ms) s0 += S.sav[jj + P.ms] * S.w.n[cn + jj];
+      const double eta = P.eta_c * (s0 + s1);
+      const double om = 1.0 - eta;
+      chv[i] = (2.0 - eta) * rcpn(2.0 * om * om * om);
+      const double nn = S.w.n[cn];
+      Xv[i] = nn * nn * chv[i] * Tv[i];
     }
-    if (jj <= P.ms) s0 += S.sav[jj + P.ms] * S.n[cn + jj];
-    const double eta = P.eta_c * (s0 + s1);
-    const double om = 1.0 - eta;
-    const double chi = (2.0 - eta) * rcpn(2.0 * om * om * om);
-    const double nn = S.n[cn];
-    S.chi[c] = chi;
-    S.X[c] = nn * nn * chi * S.T[c];
   }
-  __syncthreads();
 
   // ---- 3. node fields of the own node -------------------------------------
   const int jw = lane < WC ? lane : WC - 1;  // lane 63 mirrors lane 62 (no node)
   const int c = jw + 2, cn = jw + hn;
-  const double n = S.n[cn], u = S.u[c], T = S.T[c], chi = S.chi[c];
+  const double n = S.w.n[cn];
   const double idx12 = P.inv_dx * (1.0 / 12.0);
   double Fx = P.g_ext;
   if (P.force_model == EVLB_FORCE_EV1) {
     double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
     int m = 1;
     for (; m + 3 <= P.mf; m += 4) {
-      s0 += S.cf[m - 1] * (S.n[cn + m] - S.n[cn - m]);
-      s1 += S.cf[m] * (S.n[cn + m + 1] - S.n[cn - m - 1]);
-      s2 += S.cf[m + 1] * (S.n[cn + m + 2] - S.n[cn - m - 2]);
-      s3 += S.cf[m + 2] * (S.n[cn + m + 3] - S.n[cn - m - 3]);
+      s0 += S.cf[m - 1] * (S.w.n[cn + m] - S.w.n[cn - m]);
+      s1 += S.cf[m] * (S.w.n[cn + m + 1] - S.w.n[cn - m - 1]);
+      s2 += S.cf[m + 1] * (S.w.n[cn + m + 2] - S.w.n[cn - m - 2]);
+      s3 += S.cf[m + 2] * (S.w.n[cn + m + 3] - S.w.n[cn - m - 3]);
     }
-    for (; m <= P.mf; ++m) s0 += S.cf[m - 1] * (S.n[cn + m] - S.n[cn - m]);
+    for (; m <= P.mf; ++m) s0 += S.cf[m - 1] * (S.w.n[cn + m] - S.w.n[cn - m]);
     Fx += (s0 + s1) + (s2 + s3);
   } else if (P.force_model == EVLB_FORCE_EV2) {
-    const double d1 = (S.n[cn - 2] - 8.0 * S.n[cn - 1] + 8.0 * S.n[cn + 1] - S.n[cn + 2]) * idx12;
-    const double d3 = (-S.n[cn - 2] + 2.0 * S.n[cn - 1] - 2.0 * S.n[cn + 1] + S.n[cn + 2]) *
+    const double d1 = (S.w.n[cn - 2] - 8.0 * S.w.n[cn - 1] + 8.0 * S.w.n[cn + 1] - S.w.n[cn + 2]) * idx12;
+    const double d3 = (-S.w.n[cn - 2] + 2.0 * S.w.n[cn - 1] - 2.0 * S.w.n[cn + 1] + S.w.n[cn + 2]) *
                       (0.5 * P.inv_dx * P.inv_dx * P.inv_dx);
     Fx += P.two_a * d1 + P.kappa * d3;
   }
+  __syncthreads();  // the density window is dead: u, T and X take its place
+#pragma unroll
+  for (int i = 0; i < LU; ++i) {
+    const int cc = lane + 64 * i;
+    if (cc < WC + 4) {
+      S.w.g.u[cc] = uv[i];
+      S.w.g.T[cc] = Tv[i];
+      S.w.g.X[cc] = Xv[i];
+    }
+  }
+  // chi of the own node (c = jw + 2) from the lane that formed it
+  const int csrc = c < 64 ? c : c - 64;
+  const double chA = __shfl(chv[0], csrc), chB = __shfl(chv[LU - 1], csrc);
+  const double chi = c < 64 ? chA : chB;
+  __syncthreads();
+  const double u = S.w.g.u[c], T = S.w.g.T[c];
   const double invT = rcpn(T);
-  const double Ag = (S.X[c - 2] - 8.0 * S.X[c - 1] + 8.0 * S.X[c + 1] - S.X[c + 2]) * idx12 * rcpn(S.X[c]);
-  const double Bg = (S.T[c - 2] - 8.0 * S.T[c - 1] + 8.0 * S.T[c + 1] - S.T[c + 2]) * idx12 * invT;
-  const double Ug = (S.u[c - 2] - 8.0 * S.u[c - 1] + 8.0 * S.u[c + 1] - S.u[c + 2]) * idx12;
+  const double* Xs = S.w.g.X;
+  const double* Ts = S.w.g.T;
+  const double* us = S.w.g.u;
+  const double Ag = (Xs[c - 2] - 8.0 * Xs[c - 1] + 8.0 * Xs[c + 1] - Xs[c + 2]) * idx12 * rcpn(Xs[c]);
+  const double Bg = (Ts[c - 2] - 8.0 * Ts[c - 1] + 8.0 * Ts[c + 1] - Ts[c + 2]) * idx12 * invT;
+  const double Ug = (us[c - 2] - 8.0 * us[c - 1] + 8.0 * us[c + 1] - us[c + 2]) * idx12;
   const double bn = P.b * n;
   const double y = bn * chi;
   const double c12 = 0.16 * (1.0 + 12.0 / M_PI);
