@@ -1460,7 +1460,7 @@ __global__ __launch_bounds__(SHAPE::NT) void persistent_kernel(DevParams P, Pers
       A.beta = b_s[s];
       A.first = s == 0;
       A.rhs_mode = 0;
-      for (int t = blockIdx.x; t < P.ntiles; t += gridDim.x) SHAPE::tile(P, A, t, S, vel, meq, dpm);
+      for (int b = blockIdx.x; b < P.ntiles; b += gridDim.x) SHAPE::tile(P, A, xcd_tile(b, P.ntiles), S, vel, meq, dpm);
       if (!grid_barrier(P, gridDim.x, epoch++)) return;
     }
   }
