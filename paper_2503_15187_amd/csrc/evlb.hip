@@ -1018,7 +1018,7 @@ __global__ __launch_bounds__(W * NG) void stage_kernel(DevParams P, StageArgs A)
   } else {
     __shared__ Smem<Q, W, NG> S;
     load_tables<Q, W, NG>(P, S);
-    for (int t = blockIdx.x; t < P.ntiles; t += gridDim.x) stage_tile<Q, W, NG>(P, A, t, S);
+    for (int b = blockIdx.x; b < P.ntiles; b += gridDim.x) stage_tile<Q, W, NG>(P, A, xcd_tile(b, P.ntiles), S);
   }
 }
 
