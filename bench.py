@@ -347,8 +347,8 @@ def main():
                     help="after timing, run one 256 MiB device-to-device copy (a reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only; the multi-GPU (domain-decomposed) path is "
-              "not part of it. Run with --gpus 1.", file=sys.stderr)
+        print("bench.py: the library runs on one GPU only; a multi-GPU (domain-decomposed) path is "
+              "not implemented. Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     import torch
