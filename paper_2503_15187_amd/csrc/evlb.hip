@@ -1651,8 +1651,9 @@ Layout make_layout(const evlb_params* p) {
     L.adj_fa = off; off += align256(sizeof(double) * NFA * (size_t)L.ntot);
     L.adj_fb = off; off += align256(sizeof(double) * NFB * (size_t)L.ntot);
     L.adj_mom = off; off += mbytes;
-    // parameter partials: per VJP one slot per field-adjoint tile (16 nodes) and per node tile
-    L.adj_part = off; off += align256(sizeof(double) * 2 * 3 * (size_t)(L.ntiles_narrow + L.ntiles_adj));
+    // parameter partials: per VJP one slot per field-adjoint tile (16 nodes) and per node tile, for two
+    // steps (a step's partials are summed while the next step runs)
+    L.adj_part = off; off += align256(sizeof(double) * 2 * 2 * 3 * (size_t)(L.ntiles_narrow + L.ntiles_adj));
     L.adj_lam = off; off += fbytes;
   }
   L.total = off;
@@ -1853,7 +1854,7 @@ template <int Q>
 int launch_vjp(evlb_ctx* c, const double* f, const double* mom, const double* v, double* out, const double* X1,
                const double* X2, double cc, double a1, double a2, double pw, int vjp_index, hipStream_t st,
                double* vinj = nullptr, const double* obs = nullptr, const double* wts = nullptr, int j = 0,
-               bool final_reduce = false, double* dparams = nullptr) {
+               bool final_reduce = false, double* dparams = nullptr, int par = 0, bool sum_prev = false) {
   const DevParams P = params_adj(c);
   AdjArgs A;
   A.f = f;
@@ -1873,17 +1874,24 @@ int launch_vjp(evlb_ctx* c, const double* f, const double* mom, const double* v,
   A.obs = obs;
   A.w = wts;
   A.j = j;
-  double* part = (double*)(c->ws + c->L.adj_part);
   const int nta = P.ntiles;
   const DevParams Pn = params_for(c, NARROW);
   const int ntn = Pn.ntiles;
-  // slots of VJP i: ntn field-adjoint tiles, then nta node tiles
+  const int nslots = 3 * (ntn + nta);  // one step: three VJPs
+  // slots of step parity par, VJP i: ntn field-adjoint tiles, then nta node tiles
+  double* part = (double*)(c->ws + c->L.adj_part) + (size_t)par * 2 * nslots;
+  // with sum_prev, one extra field workgroup sums the other parity's slots
+  // (the previous step, complete by stream order) into dparams
+  A.rpart = sum_prev ? (const double*)(c->ws + c->L.adj_part) + (size_t)(par ^ 1) * 2 * nslots : nullptr;
+  A.rslots = nslots;
+  A.rdp = dparams;
   A.part = part + (size_t)vjp_index * 2 * (ntn + nta);
-  hipLaunchKernelGGL((adj_fields_kernel<Q>), dim3(ntn), dim3(WN * Q), 0, st, Pn, A);
+  hipLaunchKernelGGL((adj_fields_kernel<Q>), dim3(ntn + (sum_prev ? 1 : 0)), dim3(WN * Q), 0, st, Pn, A);
   EVLB_HIP(hipGetLastError());
+  A.rpart = nullptr;
   A.part = part + ((size_t)vjp_index * (ntn + nta) + ntn) * 2;
   hipLaunchKernelGGL((adj_column_kernel<Q>), dim3(nta * (2 * Q / NCW)), dim3(64 * NCW), 0, st, P, A,
-                     final_reduce ? 1 : 0, (const double*)part, 3 * (ntn + nta), dparams);
+                     final_reduce ? 1 : 0, (const double*)part, nslots, dparams);
   EVLB_HIP(hipGetLastError());
   return EVLB_OK;
 }
@@ -1893,22 +1901,27 @@ template <int Q>
 int adjoint_core(evlb_ctx* c, const double* fn, const double* mn, const double* f1, const double* m1,
                  const double* f2, const double* m2, const double* lam3, double* lam0, double* dparams,
                  hipStream_t st, double* lam3_inject = nullptr, const double* obs = nullptr,
-                 const double* wts = nullptr, int j = 0) {
+                 const double* wts = nullptr, int j = 0, int par = 0, bool sum_prev = false,
+                 bool final_reduce = true) {
   double* mu2 = (double*)(c->ws + c->L.adj_mu2);
   double* mu1 = (double*)(c->ws + c->L.adj_mu1);
   const double dt = c->p.dt;
   // f^{n+1} = 1/3 f^n + 2/3 (f2 + dt L(f2)):   mu2 = 2/3 (lam3 + dt J(f2)^T lam3)
   // (with an observable: lam3 += w[j] obs first, stored back into lam3)
+  // (with sum_prev, the previous step's parameter partials are summed into
+  // dparams beside the first kernel)
   int rc = launch_vjp<Q>(c, f2, m2, lam3, mu2, nullptr, nullptr, 2.0 / 3.0, 0.0, 0.0, dt * 2.0 / 3.0, 0, st,
-                         lam3_inject, obs, wts, j);
+                         lam3_inject, obs, wts, j, false, dparams, par, sum_prev);
   if (rc) return rc;
   // f2 = 3/4 f^n + 1/4 (f1 + dt L(f1)):          mu1 = 1/4 (mu2 + dt J(f1)^T mu2)
-  rc = launch_vjp<Q>(c, f1, m1, mu2, mu1, nullptr, nullptr, 0.25, 0.0, 0.0, dt * 0.25, 1, st);
+  rc = launch_vjp<Q>(c, f1, m1, mu2, mu1, nullptr, nullptr, 0.25, 0.0, 0.0, dt * 0.25, 1, st, nullptr, nullptr,
+                     nullptr, 0, false, nullptr, par);
   if (rc) return rc;
   // f1 = f^n + dt L(f^n):  lam^n = mu1 + dt J(f^n)^T mu1 + 1/3 lam3 + 3/4 mu2
-  // (its final kernel adds the step's parameter derivatives to dparams)
+  // (with final_reduce its last kernel adds the step's parameter derivatives
+  // to dparams; otherwise the next step's first kernel does)
   return launch_vjp<Q>(c, fn, mn, mu1, lam0, lam3, mu2, 1.0, 1.0 / 3.0, 0.75, dt, 2, st, nullptr, nullptr, nullptr, 0,
-                       true, dparams);
+                       final_reduce, dparams, par);
 }
 
 template <int Q>
@@ -1986,8 +1999,12 @@ int run_adjoint_record(evlb_ctx* c, const double* rec, int nsteps, double* lam, 
     const double* r = rec + (size_t)j * R;
     double* nxt = cur == lam ? other : lam;
     const bool inj = obs && wts;
+    // step s of the pass keeps its parameter partials in parity s & 1; the
+    // next step sums them beside its first kernel, and the last step sums its
+    // own in its last kernel
+    const int s = nsteps - 1 - j;
     int rc = adjoint_core<Q>(c, r, r + 3 * fs, r + fs, r + 3 * fs + 4 * nt, r + 2 * fs, r + 3 * fs + 8 * nt, cur, nxt,
-                             dparams, st, inj ? cur : nullptr, obs, wts, j);
+                             dparams, st, inj ? cur : nullptr, obs, wts, j, s & 1, s > 0, j == 0);
     if (rc) return rc;
     cur = nxt;
   }
