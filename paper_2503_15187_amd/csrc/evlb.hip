@@ -1014,11 +1014,13 @@ __global__ __launch_bounds__(W * NG) void stage_kernel(DevParams P, StageArgs A)
                  "s"(P.two_a), "s"(P.kappa), "s"(P.T_iso), "s"(P.tiso));
     asm volatile("" ::"s"(A.f_prev), "s"(A.f_n), "s"(A.f_out), "s"(A.mom_in), "s"(A.mom_out), "s"(A.alpha),
                  "s"(A.beta), "s"(A.first), "s"(A.rhs_mode));
-    for (int b = blockIdx.x; b < P.ntiles; b += gridDim.x) stage_tile_narrow<Q>(P, A, xcd_tile(b, P.ntiles), S);
+    // one tile per workgroup (the grid is the tile count): no loop, so no
+    // wait at a loop head for loads still in flight
+    if ((int)blockIdx.x < P.ntiles) stage_tile_narrow<Q>(P, A, xcd_tile(blockIdx.x, P.ntiles), S);
   } else {
     __shared__ Smem<Q, W, NG> S;
     load_tables<Q, W, NG>(P, S);
-    for (int b = blockIdx.x; b < P.ntiles; b += gridDim.x) stage_tile<Q, W, NG>(P, A, xcd_tile(b, P.ntiles), S);
+    if ((int)blockIdx.x < P.ntiles) stage_tile<Q, W, NG>(P, A, xcd_tile(blockIdx.x, P.ntiles), S);
   }
 }
 
@@ -1353,7 +1355,8 @@ __global__ __launch_bounds__(64) void stage_kernel_col(DevParams P, StageArgs A,
                                                        const double* __restrict__ meq,
                                                        const double* __restrict__ dpm) {
   __shared__ SmemCol<Q> S;
-  for (int b = blockIdx.x; b < P.ntiles; b += gridDim.x) stage_tile_col<Q>(P, A, xcd_tile(b, P.ntiles), S, vel, meq, dpm);
+  // one tile per workgroup (the grid is the tile count)
+  if ((int)blockIdx.x < P.ntiles) stage_tile_col<Q>(P, A, xcd_tile(blockIdx.x, P.ntiles), S, vel, meq, dpm);
 }
 
 // Grid-wide barrier for the persistent kernel (all workgroups co-resident:
