@@ -21,6 +21,7 @@ host core.
 import argparse
 import json
 import os
+import platform
 import sys
 import time
 
@@ -65,7 +66,22 @@ def cpu_baseline(c, n, u, T, target_s=15.0):
     rate = c["nx"] * c["Q"] * 3 * steps / el
     return {"value": rate, "unit": "updates/s", "cores": 1, "kind": "oracle",
             "sample": f"{steps} RK3 steps of the {c['nx']}-node Q={c['Q']} slab workload "
-                      f"({el:.1f} s, numpy FP64, 1 thread)"}
+                      f"({el:.1f} s, numpy FP64, 1 thread)",
+            "host": host_cpu()}
+
+
+def host_cpu():
+    """CPU model and the logical CPUs this process may run on."""
+    model = platform.processor() or platform.machine()
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"model": model, "cpus": len(os.sched_getaffinity(0))}
 
 
 def measured_traffic(workload, kernel):
