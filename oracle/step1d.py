@@ -103,8 +103,8 @@ def third_derivative(g, dx):
 
 
 def vlasov_force_ev2(n, p: Params):
-    """eq:F2: F = 2 a dn/dx + kappa d3n/dx3 (1D).  Parity unpinned beyond
-    the long-wave and linear-profile checks."""
+    """eq:F2: F = 2 a dn/dx + kappa d3n/dx3 (1D), both derivatives by the
+    5-point central stencils."""
     a = model.attraction_parameter(p.sigma, p.phi, p.gamma)
     kap = model.gradient_coefficient(p.sigma, p.phi, p.gamma)
     return 2.0 * a * central_gradient(n, p.dx) + kap * third_derivative(n, p.dx)

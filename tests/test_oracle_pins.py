@@ -658,6 +658,30 @@ def test_ev2_force_on_sinusoid():
     assert np.max(np.abs(got - ref)) < 1e-3 * np.max(np.abs(ref))
 
 
+@pytest.mark.parametrize("m", [1, 7, 64, 200, 255])
+def test_ev2_force_exact_discrete_symbol(m):
+    """eq:F2 with the paper's 5-point stencils on any Fourier mode of the
+    periodic grid: on cos(k x) with theta = k dx the 4th-order gradient gives
+    -(8 sin theta - sin 2 theta) / (6 dx) sin(k x) and the central third
+    derivative -(sin 2 theta - 2 sin theta) / dx^3 sin(k x), exactly.  With
+    a = 4 pi / 3 and kappa = 4 pi / 5 at gamma = 6 this fixes the force at
+    every wavenumber up to the Nyquist range (a wrong stencil weight, sign
+    or coefficient fails at some m)."""
+    N, dx = 512, 1 / 8
+    p = Params(Q=16, dx=dx, dt=1e-3, force_model=model.FORCE_EV2)
+    tb = step1d.Tables(p)
+    x = np.arange(N) * dx
+    th = 2 * np.pi * m / N
+    k = th / dx
+    got = step1d.vlasov_force(0.3 + 0.01 * np.cos(k * x), tb)
+    s1 = (8 * np.sin(th) - np.sin(2 * th)) / (6 * dx)
+    s3 = (np.sin(2 * th) - 2 * np.sin(th)) / dx ** 3
+    ref = -0.01 * (2 * (4 * np.pi / 3) * s1 + (4 * np.pi / 5) * s3) * np.sin(k * x)
+    # rounding scale: amplitude x the absolute weight sums of both stencils
+    scale = 0.01 * (2 * (4 * np.pi / 3) * 18 / (12 * dx) + (4 * np.pi / 5) * 6 / (2 * dx ** 3))
+    assert np.max(np.abs(got - ref)) < 1e-12 * scale
+
+
 # ---------------------------------------------------------------------------
 # isothermal mode (Sec. III A keeps the fluid temperature constant)
 # ---------------------------------------------------------------------------
