@@ -12,7 +12,7 @@ import pytest
 from numpy.polynomial import hermite_e
 from scipy import integrate
 
-from oracle import model, step1d
+from oracle import model, quadrature, step1d
 from oracle.model import Params, TERM_ADV, TERM_FORCE, TERM_J0, TERM_J1, FORCE_NONE
 from oracle.quadrature import (gauss_hermite, hermite_table, equilibrium_matrix,
                                momentum_derivative_matrix)
@@ -737,3 +737,57 @@ def test_isothermal_stationary_and_conservation():
     F1, G1 = step1d.run(F, G, tb, 5)
     assert abs(F1.sum() - F.sum()) < 1e-13 * F.sum()
     assert abs((v * F1).sum() - (v * F).sum()) < 1e-13 * np.sum(np.abs(v) * F)
+
+
+# ---------------------------------------------------------------------------
+# direct pins of helpers otherwise checked only through their callers
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n,u,T", [(0.4, 0.3, 0.6), (1.0, -0.5, 1.4), (0.2, 0.0, 0.8)])
+def test_hermite_moments_maxwellian_by_quadrature(n, u, T):
+    """a_l = n E[He_l(p)] for p ~ N(u, T), by 60-point Gauss-Hermite
+    quadrature in the standardised variable (exact for these degrees)."""
+    Q = 24
+    x, w = hermite_e.hermegauss(60)
+    w = w / np.sqrt(2 * np.pi)
+    p = u + np.sqrt(T) * x
+    got = quadrature.hermite_moments_maxwellian(n, u, T, Q)
+    for l in range(Q):
+        c = np.zeros(l + 1)
+        c[l] = 1.0
+        he = hermite_e.hermeval(p, c)
+        ref = n * np.sum(w * he)
+        scale = n * np.sum(w * np.abs(he))
+        assert abs(got[l] - ref) < 1e-12 * scale, (l, got[l], ref)
+
+
+@pytest.mark.parametrize("gamma,sigma", [(6.0, 1.0), (7.0, 0.8), (9.0, 1.3)])
+def test_force_kernel_moments_give_a_and_kappa(gamma, sigma):
+    """Expanding n(x + s) in eq:F1 to third order gives eq:F2: the first
+    and third moments of the planar kernel K are 2 a and 6 kappa.  The
+    integrals run over the kernel itself (scipy quad), so K, a and kappa are
+    pinned against each other at several gamma and sigma."""
+    p = Params(Q=16, dx=0.125, dt=1e-3, sigma=sigma, phi=1.3, gamma=gamma)
+    K = lambda s: float(model.force_kernel_1d(np.array([s]), p)[0])
+    m1 = 2 * (integrate.quad(lambda s: K(s) * s, 0, sigma, epsabs=0, epsrel=1e-13)[0]
+              + integrate.quad(lambda s: K(s) * s, sigma, np.inf, epsabs=0, epsrel=1e-13)[0])
+    m3 = 2 * (integrate.quad(lambda s: K(s) * s ** 3, 0, sigma, epsabs=0, epsrel=1e-13)[0]
+              + integrate.quad(lambda s: K(s) * s ** 3, sigma, np.inf, epsabs=0, epsrel=1e-13)[0])
+    a = model.attraction_parameter(sigma, 1.3, gamma)
+    kap = model.gradient_coefficient(sigma, 1.3, gamma)
+    assert abs(m1 - 2 * a) < 1e-11 * a
+    assert abs(m3 - 6 * kap) < 1e-11 * kap
+
+
+@pytest.mark.parametrize("M2", [2, 8, 40])
+def test_simpson_pattern_exact_on_cubics(M2):
+    """Composite Simpson weights integrate cubics exactly over M2 panels."""
+    h = 0.37
+    x = np.arange(M2 + 1) * h
+    f = lambda y: 1.0 + y - 2.0 * y ** 2 + 3.0 * y ** 3
+    L = M2 * h
+    exact = L + L ** 2 / 2 - 2 * L ** 3 / 3 + 3 * L ** 4 / 4
+    got = h * np.sum(model.simpson_pattern(M2) * f(x))
+    assert abs(got - exact) < 1e-12 * abs(exact)
+    with pytest.raises(ValueError):
+        model.simpson_pattern(M2 + 1)
