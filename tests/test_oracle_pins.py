@@ -791,3 +791,15 @@ def test_simpson_pattern_exact_on_cubics(M2):
     assert abs(got - exact) < 1e-12 * abs(exact)
     with pytest.raises(ValueError):
         model.simpson_pattern(M2 + 1)
+
+
+def test_slab_loss_on_a_uniform_state():
+    """A uniform state at rest is stationary: the flux term vanishes and the
+    objective reduces to 1/2 dx sum (n0 - n*)^2."""
+    from oracle import loss
+    N, dx, n0 = 32, 0.25, 0.3
+    rng = np.random.default_rng(4)
+    target = n0 + 0.05 * rng.standard_normal(N)
+    L = loss.slab_loss(np.full(N, n0), 0.9, 16, dx, 5e-3, 3, 7, target)
+    ref = 0.5 * dx * np.sum((n0 - target) ** 2)
+    assert abs(L - ref) < 1e-13 * ref
