@@ -398,3 +398,35 @@ def test_isothermal_2d_rhs_equals_thermal_at_uniform_temperature():
     LFi, LGi = step2d.rhs(F, G, tbi)
     assert np.max(np.abs(LFi - LF)) < 1e-12 * np.max(np.abs(LF))
     assert np.max(np.abs(LGi - LG)) < 1e-12 * np.max(np.abs(LG))
+
+
+@pytest.mark.parametrize("mx,my", [(1, 3), (7, 2), (15, 11)])
+def test_gradients_2d_exact_discrete_symbol(mx, my):
+    """Dx and Dy are the 4th-order central stencil along x (last axis) and
+    y: on cos(kx x + ky y) each gives -(8 sin t - sin 2t) / (6 dx) sin(...)
+    with t = k dx of its own axis, exactly."""
+    ny, nx, dx = 24, 32, 0.25
+    y, x = np.meshgrid(np.arange(ny) * dx, np.arange(nx) * dx, indexing="ij")
+    tx, ty = 2 * np.pi * mx / nx, 2 * np.pi * my / ny
+    g = np.cos(tx / dx * x + ty / dx * y)
+    sn = np.sin(tx / dx * x + ty / dx * y)
+    sym = lambda t: (8 * np.sin(t) - np.sin(2 * t)) / (6 * dx)
+    assert np.max(np.abs(step2d.Dx(g, dx) + sym(tx) * sn)) < 1e-13
+    assert np.max(np.abs(step2d.Dy(g, dx) + sym(ty) * sn)) < 1e-13
+
+
+def test_momentum_derivative_2d_acts_on_its_own_axis():
+    """On a separable velocity profile f[k, l] = g[k] h[l] (per node), the
+    x-derivative is (Dp g)[k] h[l] and the y-derivative g[k] (Dp h)[l]; Dp is
+    not symmetric, so a transposed or swapped operand fails."""
+    tb = step2d.Tables2D(Params(Q=8, dx=0.25, dt=1e-3))
+    Q = 8
+    rng = np.random.default_rng(11)
+    g, h = rng.standard_normal((Q, 3)), rng.standard_normal((Q, 3))
+    f = g[:, None, :] * h[None, :, :]
+    Dp = tb.Dp
+    assert np.max(np.abs(Dp - Dp.T)) > 1e-3
+    ref_x = np.stack([sum(Dp[k, j] * g[j] for j in range(Q)) for k in range(Q)])[:, None, :] * h[None, :, :]
+    ref_y = g[:, None, :] * np.stack([sum(Dp[l, j] * h[j] for j in range(Q)) for l in range(Q)])[None, :, :]
+    assert np.max(np.abs(step2d.dp_x(f, tb) - ref_x)) < 1e-12
+    assert np.max(np.abs(step2d.dp_y(f, tb) - ref_y)) < 1e-12
