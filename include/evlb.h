@@ -142,7 +142,9 @@ size_t evlb_workspace_bytes(const evlb_params* params);
 /* Builds the quadrature (roots of He_q, normalised Christoffel weights),
  * the Hermite equilibrium and momentum-derivative tables, the Simpson
  * weights of the averaged density (Sec. II A) and of the force (eq:F1),
- * copies them into d_workspace on hip_stream and returns a context in
+ * enqueues their copies into d_workspace (and the clearing of the status
+ * latch) on hip_stream, then synchronises hip_stream before returning (the
+ * host staging buffers do not outlive the call), and returns a context in
  * *out.  d_workspace: device, >= evlb_workspace_bytes(params) bytes,
  * owned by the caller.  The context keeps a copy of params (and of nx). */
 int evlb_init(const evlb_params* params, void* d_workspace, size_t ws_bytes,
@@ -222,8 +224,9 @@ int evlb_equilibrium_adjoint(evlb_ctx* ctx, const double* d_n, const double* d_u
                              const double* d_T, const double* d_lam, double* d_nbar,
                              double* d_ubar, double* d_Tbar, void* hip_stream);
 
-/* Synchronises hip_stream and reports the latched device status:
- * EVLB_OK or EVLB_ENONFINITE.  Clears the latch when clear != 0. */
+/* Enqueues a copy of the latched device status to the host (and, when
+ * clear != 0, its clearing) on hip_stream, synchronises hip_stream and
+ * reports it: EVLB_OK or EVLB_ENONFINITE. */
 int evlb_status(evlb_ctx* ctx, void* hip_stream, int32_t clear);
 
 /* Node count n_tot and quadrature nodes (host copy, length q) of a context. */

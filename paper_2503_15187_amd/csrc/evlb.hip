@@ -2063,7 +2063,7 @@ int evlb_init(const evlb_params* params, void* d_workspace, size_t ws_bytes, voi
     c->nx.assign(params->nx, params->nx + 1);
     c->p.nx = c->nx.data();
     if (hipGetDevice(&c->device) != hipSuccess) { delete c; return EVLB_EHIP; }
-    rc = evlb2d::init(params, (char*)d_workspace, ws_bytes, &c->c2);
+    rc = evlb2d::init(params, (char*)d_workspace, ws_bytes, (hipStream_t)hip_stream, &c->c2);
     if (rc) { delete c; return rc; }
     c->ws = (char*)d_workspace;
     c->vel = evlb2d::velocities(c->c2);
@@ -2118,29 +2118,32 @@ int evlb_init(const evlb_params* params, void* d_workspace, size_t ws_bytes, voi
   }
   hipStream_t st = (hipStream_t)hip_stream;
   double* tab = (double*)(c->ws + L.tables);
-  // synchronous copies: the host vectors die when this call returns
-  if (hipMemcpy(tab, host.data(), host.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemcpy(c->ws + L.tiles_wide, tw.data(), tw.size() * sizeof(int4), hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemcpy(c->ws + L.tiles_narrow, tn.data(), tn.size() * sizeof(int4), hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemcpy(c->ws + L.tiles_col, tc.data(), tc.size() * sizeof(int4), hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemcpy(c->ws + L.tiles_adj, ta.data(), ta.size() * sizeof(int4), hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemset(c->ws + L.status, 0, 256) != hipSuccess) {
-    delete c;
-    return EVLB_EHIP;
-  }
+  // the per-system temperatures expanded to one value per node
+  std::vector<double> tn_node;
   if (params->T_iso_sys) {
-    // the per-system temperatures expanded to one value per node
-    std::vector<double> tn_node((size_t)L.ntot);
+    tn_node.resize((size_t)L.ntot);
     size_t o = 0;
     for (int s = 0; s < params->n_sys; ++s)
       for (int i = 0; i < params->nx[s]; ++i) tn_node[o++] = params->T_iso_sys[s];
-    if (hipMemcpy(c->ws + L.tiso, tn_node.data(), tn_node.size() * sizeof(double), hipMemcpyHostToDevice) !=
-        hipSuccess) {
-      delete c;
-      return EVLB_EHIP;
-    }
   }
-  (void)st;
+  // copies ordered on the caller's stream; the stream is synchronised before
+  // returning because the host vectors die with this call
+  if (hipMemcpyAsync(tab, host.data(), host.size() * sizeof(double), hipMemcpyHostToDevice, st) != hipSuccess ||
+      hipMemcpyAsync(c->ws + L.tiles_wide, tw.data(), tw.size() * sizeof(int4), hipMemcpyHostToDevice, st) !=
+          hipSuccess ||
+      hipMemcpyAsync(c->ws + L.tiles_narrow, tn.data(), tn.size() * sizeof(int4), hipMemcpyHostToDevice, st) !=
+          hipSuccess ||
+      hipMemcpyAsync(c->ws + L.tiles_col, tc.data(), tc.size() * sizeof(int4), hipMemcpyHostToDevice, st) !=
+          hipSuccess ||
+      hipMemcpyAsync(c->ws + L.tiles_adj, ta.data(), ta.size() * sizeof(int4), hipMemcpyHostToDevice, st) !=
+          hipSuccess ||
+      hipMemsetAsync(c->ws + L.status, 0, 256, st) != hipSuccess ||
+      (params->T_iso_sys && hipMemcpyAsync(c->ws + L.tiso, tn_node.data(), tn_node.size() * sizeof(double),
+                                           hipMemcpyHostToDevice, st) != hipSuccess) ||
+      hipStreamSynchronize(st) != hipSuccess) {
+    delete c;
+    return EVLB_EHIP;
+  }
   DevParams& d = c->dp;
   d.vel = tab;
   d.meq = tab + q;
@@ -2253,10 +2256,11 @@ int evlb_adjoint_record(evlb_ctx* ctx, const double* d_rec, int32_t nsteps, doub
 int evlb_status(evlb_ctx* ctx, void* hip_stream, int32_t clear) {
   if (!ctx) return EVLB_EINVAL;
   hipStream_t st = (hipStream_t)hip_stream;
-  if (hipStreamSynchronize(st) != hipSuccess) return EVLB_EHIP;
   int h[2] = {0, 0};
-  if (hipMemcpy(h, ctx->dp.status, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess) return EVLB_EHIP;
-  if (clear && hipMemset(ctx->dp.status, 0, sizeof(h)) != hipSuccess) return EVLB_EHIP;
+  // read (and clear) the latch in stream order, then wait for both
+  if (hipMemcpyAsync(h, ctx->dp.status, sizeof(h), hipMemcpyDeviceToHost, st) != hipSuccess) return EVLB_EHIP;
+  if (clear && hipMemsetAsync(ctx->dp.status, 0, sizeof(h), st) != hipSuccess) return EVLB_EHIP;
+  if (hipStreamSynchronize(st) != hipSuccess) return EVLB_EHIP;
   if (h[1]) return EVLB_EHIP;
   return h[0] ? EVLB_ENONFINITE : EVLB_OK;
 }

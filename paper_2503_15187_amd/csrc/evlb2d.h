@@ -14,7 +14,7 @@ struct Ctx;
 
 int validate(const evlb_params* p);
 size_t workspace_bytes(const evlb_params* p);
-int init(const evlb_params* p, char* ws, size_t bytes, Ctx** out);
+int init(const evlb_params* p, char* ws, size_t bytes, hipStream_t st, Ctx** out);
 void destroy(Ctx* c);
 
 long long node_count(const Ctx* c);

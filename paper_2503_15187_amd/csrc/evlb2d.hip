@@ -844,7 +844,7 @@ size_t workspace_bytes(const evlb_params* p) {
   return make_layout(p, t).total;
 }
 
-int init(const evlb_params* p, char* ws, size_t bytes, Ctx** out) {
+int init(const evlb_params* p, char* ws, size_t bytes, hipStream_t st, Ctx** out) {
   *out = nullptr;
   int rc = validate(p);
   if (rc) return rc;
@@ -883,9 +883,11 @@ int init(const evlb_params* p, char* ws, size_t bytes, Ctx** out) {
   if (t.pair_cx.empty()) hi.push_back(0);
   double* tabd = (double*)(ws + L.tab_d);
   int* tabi = (int*)(ws + L.tab_i);
-  if (hipMemcpy(tabd, hd.data(), hd.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemcpy(tabi, hi.data(), hi.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemset(ws + L.status, 0, 256) != hipSuccess) {
+  // ordered on the caller's stream, which is synchronised before the host
+  // vectors go out of scope
+  if (hipMemcpyAsync(tabd, hd.data(), hd.size() * sizeof(double), hipMemcpyHostToDevice, st) != hipSuccess ||
+      hipMemcpyAsync(tabi, hi.data(), hi.size() * sizeof(int), hipMemcpyHostToDevice, st) != hipSuccess ||
+      hipMemsetAsync(ws + L.status, 0, 256, st) != hipSuccess || hipStreamSynchronize(st) != hipSuccess) {
     delete c;
     return EVLB_EHIP;
   }

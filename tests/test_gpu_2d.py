@@ -21,6 +21,8 @@ import workloads  # noqa: E402
 from oracle import step2d  # noqa: E402
 from oracle.model import Params, TERM_ADV, TERM_FORCE, TERM_J0, TERM_J1, FORCE_NONE  # noqa: E402
 
+from parity import check, rel  # noqa: E402
+
 pytestmark = pytest.mark.gpu
 
 E = None
@@ -39,8 +41,6 @@ def td(a):
     return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=DEV)
 
 
-def rel(got, ref):
-    return max(np.max(np.abs(got[i] - ref[i])) / np.max(np.abs(ref[i])) for i in range(2))
 
 
 def tables(c, **kw):
@@ -110,7 +110,7 @@ def test_equilibrium_and_moments_2d():
     F, G = step2d.initial_state(n, ux, uy, T, tb)
     s = solver(c, 40, 24)
     f = s.equilibrium(td(n), td(np.stack([ux, uy])), td(T)).cpu().numpy()
-    assert rel(f, [F, G]) < 1e-13
+    check(f, [F, G], 1e-13)
     Fp, Gp = oracle_state(c, n, ux, uy, T, tb)
     mom = s.moments(td(np.stack([Fp, Gp]))).cpu().numpy()
     ref = step2d.moments(Fp, Gp, tb)
@@ -131,7 +131,7 @@ def test_rhs_terms_2d(mask, nx, ny):
     LF, LG = step2d.rhs(F, G, tb)
     s = solver(c, nx, ny, **kw)
     L = s.rhs(td(np.stack([F, G]))).cpu().numpy()
-    assert rel(L, [LF, LG]) < 1e-11
+    check(L, [LF, LG], 1e-11)
 
 
 def test_rhs_force_model_none_2d():
@@ -141,7 +141,7 @@ def test_rhs_force_model_none_2d():
     F, G = oracle_state(c, n, ux, uy, T, tb)
     LF, LG = step2d.rhs(F, G, tb)
     L = solver(c, 40, 16, force_model=2, g_ext=0.02).rhs(td(np.stack([F, G]))).cpu().numpy()
-    assert rel(L, [LF, LG]) < 1e-11
+    check(L, [LF, LG], 1e-11)
 
 
 @pytest.mark.parametrize("nsteps", [1, 4])
@@ -156,7 +156,7 @@ def test_steps_2d(nsteps):
     f = td(np.stack([F, G]))
     s.step(f, nsteps)
     assert s.status() == E.EVLB_OK
-    assert rel(f.cpu().numpy(), [Fo, Go]) < 1e-11 * nsteps
+    check(f.cpu().numpy(), [Fo, Go], 1e-11, steps=nsteps)
 
 
 def test_uniform_state_stationary_2d():
@@ -236,7 +236,7 @@ def test_full_size_rhs_sampled(full_state):
         ys = torch.tensor((yc + np.arange(b)) % c["ny"], device=DEV)
         xs = torch.tensor((xc + np.arange(b)) % c["nx"], device=DEV)
         got = L.index_select(3, ys).index_select(4, xs).cpu().numpy()
-        assert rel(got, [LF[:, :, cy, cy], LG[:, :, cy, cy]]) < 1e-11, (yc, xc)
+        check(got, [LF[:, :, cy, cy], LG[:, :, cy, cy]], 1e-11, what=repr((yc, xc)))
 
 
 def test_full_size_step_sampled(full_state):
@@ -259,4 +259,4 @@ def test_full_size_step_sampled(full_state):
     P = perturbation_at(yi, xi)
     Fo, Go = step2d.rk3_step(Fw * P[0], Gw * P[1], tb)
     got = g[:, :, :, yc:yc + b, xc:xc + b].cpu().numpy()
-    assert rel(got, [Fo[:, :, m:m + b, m:m + b], Go[:, :, m:m + b, m:m + b]]) < 1e-11
+    check(got, [Fo[:, :, m:m + b, m:m + b], Go[:, :, m:m + b, m:m + b]], 1e-11)

@@ -10,6 +10,8 @@ import workloads  # noqa: E402
 from oracle import step1d  # noqa: E402
 from oracle.model import Params  # noqa: E402
 
+from parity import check, rel  # noqa: E402
+
 pytestmark = pytest.mark.gpu
 
 E = AT = None
@@ -27,8 +29,6 @@ def td(a):
     return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
 
 
-def rel(got, ref):
-    return max(np.max(np.abs(got[i] - ref[i])) / np.max(np.abs(ref[i])) for i in range(2))
 
 
 def batch(n_sys, nx_max=None):
@@ -119,7 +119,7 @@ def test_full_batch_sampled_systems_match_oracle():
         ni, ui, Ti = systems[i]
         F, G = step1d.initial_state(ni, ui, Ti, tb)
         F, G = step1d.run(F, G, tb, 3)
-        assert rel(got[:, :, offs[i]:offs[i + 1]], [F, G]) < 1e-11, (i, nxs[i])
+        check(got[:, :, offs[i]:offs[i + 1]], [F, G], 1e-11, what=repr((i, nxs[i])))
 
 
 def test_full_batch_per_system_mass_conservation():

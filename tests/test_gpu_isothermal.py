@@ -20,6 +20,8 @@ import workloads  # noqa: E402
 from oracle import model, step1d, step2d  # noqa: E402
 from oracle.model import Params  # noqa: E402
 
+from parity import check, rel  # noqa: E402
+
 pytestmark = pytest.mark.gpu
 
 E = None
@@ -37,8 +39,6 @@ def td(a):
     return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
 
 
-def rel(got, ref):
-    return max(np.max(np.abs(got[i] - ref[i])) / np.max(np.abs(ref[i])) for i in range(2))
 
 
 def _state_1d(T_iso):
@@ -61,7 +61,7 @@ def test_isothermal_rhs_1d(mask):
     LF, LG = step1d.rhs(F, G, tb)
     s = E.Solver(16, c["dx"], c["dt"], c["nx"], T_iso=T_iso, term_mask=mask)
     L = s.rhs(td(np.stack([F, G]))).cpu().numpy()
-    assert rel(L, [LF, LG]) < 1e-11
+    check(L, [LF, LG], 1e-11)
 
 
 @pytest.mark.parametrize("tile", [16, 63])
@@ -73,7 +73,7 @@ def test_isothermal_steps_1d(tile):
     f = td(np.stack([F, G]))
     s.step(f, 10)
     assert s.status() == E.EVLB_OK
-    assert rel(f.cpu().numpy(), [Fo, Go]) < 1e-10
+    check(f.cpu().numpy(), [Fo, Go], 1e-10)
 
 
 def test_isothermal_2d_rhs_and_step():
@@ -87,11 +87,11 @@ def test_isothermal_2d_rhs_and_step():
     LF, LG = step2d.rhs(F, G, tb)
     s = E.Solver(16, c["dx"], c["dt"], 40, ny=24, T_iso=T_iso)
     L = s.rhs(td(np.stack([F, G]))).cpu().numpy()
-    assert rel(L, [LF, LG]) < 1e-11
+    check(L, [LF, LG], 1e-11)
     Fo, Go = step2d.rk3_step(F, G, tb)
     f = td(np.stack([F, G]))
     s.step(f, 1)
-    assert rel(f.cpu().numpy(), [Fo, Go]) < 1e-11
+    check(f.cpu().numpy(), [Fo, Go], 1e-11)
 
 
 TEMPS = (0.55, 0.6, 0.65, 0.7, 0.74)
@@ -127,9 +127,9 @@ def test_per_system_isothermal_batch_matches_oracle(tile):
         for i, tb in enumerate(tabs):
             sl = slice(offs[i], offs[i + 1])
             F1, G1 = step1d.rk3_step(parts[i][0], parts[i][1], tb)
-            assert rel(got1[:, :, sl], [F1, G1]) < 1e-11, (i, temps[i])
+            check(got1[:, :, sl], [F1, G1], 1e-11, what=repr((i, temps[i])))
             F10, G10 = step1d.run(F1, G1, tb, 9)
-            assert rel(got10[:, :, sl], [F10, G10]) < 1e-10, (i, temps[i])
+            check(got10[:, :, sl], [F10, G10], 1e-10, what=repr((i, temps[i])))
 
 
 def test_stationary_interfaces_sec3a_on_maxwell_construction():

@@ -14,6 +14,8 @@ import workloads  # noqa: E402
 from oracle import step1d  # noqa: E402
 from oracle.model import Params  # noqa: E402
 
+from parity import check, rel  # noqa: E402
+
 pytestmark = pytest.mark.gpu
 
 E = None
@@ -34,9 +36,6 @@ def td(a):
     return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=DEV)
 
 
-def rel(got, ref):
-    """max over planes of max|got - ref| / max|ref|."""
-    return max(np.max(np.abs(got[i] - ref[i])) / np.max(np.abs(ref[i])) for i in range(2))
 
 
 def oracle_tables(c, **kw):
@@ -70,7 +69,7 @@ def test_equilibrium_and_moments_match_oracle():
         F, G = step1d.initial_state(n, u, T, tb)
         s = solver(c)
         f = s.equilibrium(td(n), td(u), td(T)).cpu().numpy()
-        assert rel(f, [F, G]) < 1e-13
+        check(f, [F, G], 1e-13)
         Fn, Gn = nonequilibrium(F, G, tb)
         mom = s.moments(td(np.stack([Fn, Gn]))).cpu().numpy()
         ref = step1d.moments(Fn, Gn, tb)
@@ -89,7 +88,7 @@ def test_rhs_matches_oracle_per_term(mask, which, tile):
     LF, LG = step1d.rhs(F, G, tb)
     s = solver(c, term_mask=mask, tile_nodes=tile)
     L = s.rhs(td(np.stack([F, G]))).cpu().numpy()
-    assert rel(L, [LF, LG]) < 1e-11
+    check(L, [LF, LG], 1e-11)
 
 
 @pytest.mark.parametrize("tile", [16, 63, 64])
@@ -103,10 +102,10 @@ def test_one_and_ten_steps_match_oracle(mode, tile):
         f = s.equilibrium(td(n), td(u), td(T))
         s.step(f, 1)
         F1, G1 = step1d.rk3_step(F, G, tb)
-        assert rel(f.cpu().numpy(), [F1, G1]) < 1e-11
+        check(f.cpu().numpy(), [F1, G1], 1e-11)
         s.step(f, 9)
         F10, G10 = step1d.run(F1, G1, tb, 9)
-        assert rel(f.cpu().numpy(), [F10, G10]) < 1e-10
+        check(f.cpu().numpy(), [F10, G10], 1e-10)
         assert s.status() == 0
 
 
@@ -122,17 +121,17 @@ def test_q8_rhs_and_steps_match_oracle(tile):
     LF, LG = step1d.rhs(F, G, tb)
     s = solver(c, tile_nodes=tile)
     L = s.rhs(td(np.stack([F, G]))).cpu().numpy()
-    assert rel(L, [LF, LG]) < 1e-11
+    check(L, [LF, LG], 1e-11)
     for mode in (1, 2):
         F0, G0 = step1d.initial_state(n, u, T, tb)
         s = solver(c, exec_mode=mode, tile_nodes=tile)
         f = s.equilibrium(td(n), td(u), td(T))
         s.step(f, 1)
         F1, G1 = step1d.rk3_step(F0, G0, tb)
-        assert rel(f.cpu().numpy(), [F1, G1]) < 1e-11
+        check(f.cpu().numpy(), [F1, G1], 1e-11)
         s.step(f, 9)
         F10, G10 = step1d.run(F1, G1, tb, 9)
-        assert rel(f.cpu().numpy(), [F10, G10]) < 1e-10
+        check(f.cpu().numpy(), [F10, G10], 1e-10)
         assert s.status() == 0
 
 
@@ -163,7 +162,7 @@ def test_ev2_and_no_force_match_oracle(force, tile):
         F, G = nonequilibrium(*step1d.initial_state(n, u, T, tb), tb)
         LF, LG = step1d.rhs(F, G, tb)
         L = solver(c, nx=N, term_mask=mask, tile_nodes=tile, **kw).rhs(td(np.stack([F, G]))).cpu().numpy()
-        assert rel(L, [LF, LG]) < 1e-11, mask
+        check(L, [LF, LG], 1e-11, what=repr(mask))
     tb = oracle_tables(c, **kw)
     F0, G0 = step1d.initial_state(n, u, T, tb)
     F1, G1 = step1d.rk3_step(F0, G0, tb)
@@ -172,9 +171,9 @@ def test_ev2_and_no_force_match_oracle(force, tile):
         s = solver(c, nx=N, exec_mode=mode, tile_nodes=tile, **kw)
         f = s.equilibrium(td(n), td(u), td(T))
         s.step(f, 1)
-        assert rel(f.cpu().numpy(), [F1, G1]) < 1e-11, mode
+        check(f.cpu().numpy(), [F1, G1], 1e-11, what=repr(mode))
         s.step(f, 9)
-        assert rel(f.cpu().numpy(), [F10, G10]) < 1e-10, mode
+        check(f.cpu().numpy(), [F10, G10], 1e-10, what=repr(mode))
         assert s.status() == 0
 
 
@@ -195,7 +194,7 @@ def test_widest_windows_match_oracle(force, tile):
     F, G = nonequilibrium(*step1d.initial_state(n, u, T, tb), tb)
     LF, LG = step1d.rhs(F, G, tb)
     L = solver(c, nx=N, tile_nodes=tile, **kw).rhs(td(np.stack([F, G]))).cpu().numpy()
-    assert rel(L, [LF, LG]) < 1e-11
+    check(L, [LF, LG], 1e-11)
     F0, G0 = step1d.initial_state(n, u, T, tb)
     F1, G1 = step1d.rk3_step(F0, G0, tb)
     F10, G10 = step1d.run(F1, G1, tb, 9)
@@ -203,9 +202,9 @@ def test_widest_windows_match_oracle(force, tile):
         s = solver(c, nx=N, exec_mode=mode, tile_nodes=tile, **kw)
         f = s.equilibrium(td(n), td(u), td(T))
         s.step(f, 1)
-        assert rel(f.cpu().numpy(), [F1, G1]) < 1e-11, mode
+        check(f.cpu().numpy(), [F1, G1], 1e-11, what=repr(mode))
         s.step(f, 9)
-        assert rel(f.cpu().numpy(), [F10, G10]) < 1e-10, mode
+        check(f.cpu().numpy(), [F10, G10], 1e-10, what=repr(mode))
         assert s.status() == 0
 
 
@@ -244,8 +243,8 @@ def test_tiny_systems_batch_matches_oracle(tile):
         assert s.status() == 0
         for i in range(len(nxs)):
             sl = slice(offs[i], offs[i + 1])
-            assert rel(got1[:, :, sl], refs[i][0]) < 1e-11, (mode, nxs[i])
-            assert rel(got10[:, :, sl], refs[i][1]) < 1e-10, (mode, nxs[i])
+            check(got1[:, :, sl], refs[i][0], 1e-11, what=repr((mode, nxs[i])))
+            check(got10[:, :, sl], refs[i][1], 1e-10, what=repr((mode, nxs[i])))
 
 
 def test_phase_separation_1000_steps_match_oracle():
@@ -257,9 +256,8 @@ def test_phase_separation_1000_steps_match_oracle():
     s = solver(c)
     f = s.equilibrium(td(n), td(u), td(T))
     s.step(f, c["steps"])
-    err = rel(f.cpu().numpy(), [F, G])
-    print(f"1000-step rel err {err:.3e}", flush=True)
-    assert err < 1e-8
+    err, rerr = check(f.cpu().numpy(), [F, G], 1e-8, steps=c["steps"])
+    print(f"1000-step rel err {err:.3e}, per row {rerr:.3e}", flush=True)
     assert s.status() == 0
 
 
@@ -273,7 +271,7 @@ def test_exec_modes_agree_and_repeat_bitwise():
         out.append(f.cpu().numpy())
     assert np.array_equal(out[0], out[2])
     for o in out[1:]:
-        assert rel(o, out[0]) < 1e-14
+        check(o, out[0], 1e-14)
 
 
 def test_ragged_batch_matches_independent_oracle_runs():
@@ -293,7 +291,7 @@ def test_ragged_batch_matches_independent_oracle_runs():
         for (ni, ui, Ti), nx in zip(systems, nxs):
             F, G = step1d.initial_state(ni, ui, Ti, tb)
             F, G = step1d.run(F, G, tb, 5)
-            assert rel(got[:, :, off:off + nx], [F, G]) < 1e-11, (mode, nx)
+            check(got[:, :, off:off + nx], [F, G], 1e-11, what=repr((mode, nx)))
             off += nx
 
 
@@ -329,7 +327,7 @@ def test_slab_full_size_ten_steps_match_oracle():
     s = solver(c)
     f = s.equilibrium(td(n), td(u), td(T))
     s.step(f, 10)
-    assert rel(f.cpu().numpy(), [F, G]) < 1e-10
+    check(f.cpu().numpy(), [F, G], 1e-10)
 
 
 def test_nonfinite_state_is_reported():

@@ -227,6 +227,34 @@ def test_dilute_limits_of_transport():
     assert abs(model.collision_rate(n, T, chi, 1.0) / (n * T / mu_hs) - 1) < 1e-8
 
 
+@pytest.mark.parametrize("y_target", [0.5, 1.0, 2.0, 3.5, 5.0])
+def test_relaxation_time_two_forms_of_eq_tau(y_target):
+    """eq:tau gives the relaxation time twice: through the shear viscosity,
+    tau = mu / (n T (1 + 2/5 b n chi)), and through the conductivity,
+    tau = lambda Pr / (5/2 n T (1 + 3/5 b n chi)) (the printed second form is
+    garbled: tau appears on both sides; this is the reading that makes the
+    two forms define eq:prandtl).  At dense states (b n chi from 0.5 to 5)
+    the oracle's relaxation time must equal the conductivity form and its
+    collision rate chi / tau; a dropped or doubled chi anywhere in the chain
+    breaks the equality."""
+    b = model.excluded_volume(1.0)
+    lo, hi = 1e-6, 0.9
+    for _ in range(200):  # density with b n chi(n) = y_target
+        mid = 0.5 * (lo + hi)
+        if b * mid * model.contact_value(mid, 1.0) < y_target:
+            lo = mid
+        else:
+            hi = mid
+    n = 0.5 * (lo + hi)
+    for T in (0.45, 0.75, 1.3):
+        chi = model.contact_value(n, 1.0)
+        y = b * n * chi
+        assert abs(y - y_target) < 1e-12
+        tau_lam = model.conductivity(n, T, chi, 1.0) * model.prandtl(n, chi, 1.0) / (2.5 * n * T * (1 + 0.6 * y))
+        assert abs(model.relaxation_time(n, T, chi, 1.0) / tau_lam - 1) < 1e-13
+        assert abs(model.collision_rate(n, T, chi, 1.0) * tau_lam / chi - 1) < 1e-13
+
+
 # ---------------------------------------------------------------------------
 # Shakhov and J1: reduction over (p_y, p_z) checked against the 3D formulas
 # ---------------------------------------------------------------------------
@@ -517,7 +545,15 @@ def test_homogeneous_relaxation_closed_form():
     F = F + eps * (tb.w * He[2])[:, None] + 0.5 * eps * (tb.w * He[3])[:, None]
     G = G - eps * tb.w[:, None]
     m = step1d.node_fields(F, G, tb)
-    nu, Pr = m["nu"][0], m["Pr"][0]
+    # the expected rate is taken from the second form of eq:tau (through the
+    # conductivity and the Prandtl number), not from the oracle's own nu:
+    # nu = chi / tau, tau = lambda Pr / (5/2 n T (1 + 3/5 b n chi)), with
+    # chi the contact value of the uniform density
+    chi = model.contact_value(n0, 1.0)
+    y = model.excluded_volume(1.0) * n0 * chi
+    Pr = model.prandtl(n0, chi, 1.0)
+    tau = model.conductivity(n0, T0, chi, 1.0) * Pr / (2.5 * n0 * T0 * (1 + 0.6 * y))
+    nu = chi / tau
     R = lambda z: 1 + z + z * z / 2 + z ** 3 / 6
     v = tb.v[:, None]
     s0 = (v ** 2 * F).sum(0)[0] - n0 * T0
