@@ -1,22 +1,24 @@
 """Throughput of the EV-FDLB time step on one MI355X.
 
-One bench step = one TVD-RK3 time step (three stages, every part of the
-method) of the slab-evaporation workload: 4096 nodes, Q = 24 Gauss-Hermite
-velocities, dx = sigma/8, liquid slab 64 sigma wide (eq:tan) at the
-coexistence densities of T/T_c = 0.8.  The metric counts site-velocity
-updates per second: nodes x velocities x 3 stages x steps / GPU time.
+Headline: the 2D phase-separation workload, the largest configuration and
+the one bound by HBM bandwidth: 1024 x 1024 periodic nodes, dx = sigma/4,
+16 x 16 tensor Gauss-Hermite velocities (plus the reduced z-energy G), T =
+0.75 T_c of the disc kernel, n0 = 0.3 with 1% Gaussian noise.  One bench
+step = one TVD-RK3 time step (three stages, every part of the method).  The
+metric counts site-velocity updates per second: nodes x velocities x 3
+stages x steps / GPU time.
 
-Secondary entries report the batched sweep (512 independent periodic systems
-of log-uniform length in [256, 8192], Q = 16, about 1.1M nodes) and the 2D
-phase separation (1024 x 1024 nodes, 16 x 16 velocities, 2.7e8
-site-velocities), the HBM-sized cases, each with its own roofline, and the
-adjoint/forward time ratio of the differentiable slab workload.
+Secondary entries: the slab-evaporation workload (4096 nodes, Q = 24, the
+latency-bound case), the batched sweep (512 independent periodic systems of
+log-uniform length in [256, 8192], Q = 16, about 1.1M nodes), the
+adjoint/forward time ratio of the differentiable slab workload, and the
+paper's own Sec. III B / III C runs (context for Table I).
 
 Prints one JSON line.  The state is resident in HBM before the timed region;
-timing uses HIP events on the stream the kernels run on.  The launch shape of
-each workload is chosen by the autotuner before timing.  The CPU baseline is
-the oracle timed on a bounded number of steps of the headline workload on one
-host core.
+timing uses HIP events on the stream the kernels run on.  The CPU baseline
+is the 2D oracle timed on periodic 128 x 128 windows of the headline
+workload, on one host core and on every core the process may use (one
+window per worker process), before the GPU is touched.
 """
 import argparse
 import json
@@ -38,8 +40,9 @@ BYTES_PER_UPDATE_STEP = 128.0
 KERNEL_NAMES = {16: "stage_kernel<{q},16,{q}>", 63: "stage_kernel_col<{q}>", 64: "stage_kernel<{q},64,8>"}
 
 
-def cpu_baseline(c, n, u, T, target_s=15.0):
-    """Oracle (numpy FP64, one thread) on a bounded sample of steps."""
+def cpu_baseline(c, n, u, T, target_s=8.0):
+    """Oracle (numpy FP64, one thread) on a bounded sample of steps of a 1D
+    workload."""
     try:
         from threadpoolctl import threadpool_limits
     except ImportError:  # pragma: no cover
@@ -67,6 +70,58 @@ def cpu_baseline(c, n, u, T, target_s=15.0):
     return {"value": rate, "unit": "updates/s", "cores": 1, "kind": "oracle",
             "sample": f"{steps} RK3 steps of the {c['nx']}-node Q={c['Q']} slab workload "
                       f"({el:.1f} s, numpy FP64, 1 thread)",
+            "host": host_cpu()}
+
+
+def _oracle_2d_window(args):
+    """One worker of the 2D CPU baseline: `steps` RK3 steps of the oracle on
+    a periodic w x w window of the headline workload (window index i picks
+    its position).  Returns (seconds, updates)."""
+    i, w, steps = args
+    try:
+        from threadpoolctl import threadpool_limits
+        lim = threadpool_limits(1)
+    except ImportError:  # pragma: no cover
+        lim = None
+    import workloads
+    from oracle import step2d
+    from oracle.model import Params
+    c, n, ux, uy, T = workloads.phase_separation_2d()
+    y0 = (i * w) % c["ny"]
+    x0 = ((i * w) // c["ny"] * w) % c["nx"]
+    cut = lambda a: np.ascontiguousarray(a[y0:y0 + w, x0:x0 + w])
+    tb = step2d.Tables2D(Params(Q=c["Q"], dx=c["dx"], dt=c["dt"]))
+    F, G = step2d.initial_state(cut(n), cut(ux), cut(uy), cut(T), tb)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        F, G = step2d.rk3_step(F, G, tb)
+    el = time.perf_counter() - t0
+    if lim is not None:
+        lim.__exit__(None, None, None)
+    return el, w * w * c["Q"] * c["Q"] * 3 * steps
+
+
+def cpu_baseline_2d(w=128, steps=3, max_workers=16):
+    """The 2D oracle (numpy FP64) on periodic w x w windows cut from the
+    headline workload: one worker on one core, then one worker per core the
+    process may use (at most max_workers), each on its own window, all
+    started together; the rate is total updates over the slowest worker's
+    time.  Worker processes are forked before this process touches the
+    GPU."""
+    import multiprocessing as mp
+    el1, up1 = _oracle_2d_window((0, w, steps))
+    cores = max(1, min(max_workers, len(os.sched_getaffinity(0))))
+    ctx = mp.get_context("fork")
+    with ctx.Pool(cores) as pool:
+        res = pool.map(_oracle_2d_window, [(i, w, steps) for i in range(cores)])
+    el_all = max(r[0] for r in res)
+    up_all = sum(r[1] for r in res)
+    return {"value": up_all / el_all, "unit": "updates/s", "cores": cores, "kind": "oracle",
+            "sample": f"{steps} RK3 steps of the 2D oracle (numpy FP64, one thread per process) on each of "
+                      f"{cores} periodic {w}x{w} windows of the 1024x1024 16x16-velocity workload, one "
+                      f"window per process, all cores together ({el_all:.1f} s)",
+            "value_1core": up1 / el1,
+            "sample_1core": f"{steps} RK3 steps on one {w}x{w} window, one process, one thread ({el1:.1f} s)",
             "host": host_cpu()}
 
 
@@ -237,9 +292,10 @@ def paper_runs(E, torch, dev, steps_3b=None):
     """The paper's own runs at its parameters (dx = sigma/10, dt = 5e-3,
     Q = 16), timed end to end for comparison with the single-core runtimes of
     Table I (context, not a target): Sec. III B, the four phase-separation
-    runs of eq:rho_init_takata to t = 5000 (1e6 steps), and Sec. III C, the
-    four evaporation runs to t = 75 (15000 steps), each set as one batched
-    launch sequence, with EV1 and with EV2."""
+    runs of eq:rho_init_takata to t = 5000 (1e6 steps; steps_3b shortens
+    them and the time per run is scaled to the paper's step count), and
+    Sec. III C, the four evaporation runs to t = 75 (15000 steps), each set
+    as one batched launch sequence, with EV1 and with EV2."""
     import workloads
     td = lambda a: torch.tensor(a, dtype=torch.float64, device=dev)
     out = []
@@ -268,7 +324,10 @@ def paper_runs(E, torch, dev, steps_3b=None):
                         "metric": "wall time of the batched runs", "value": wall, "unit": "s",
                         "higher_is_better": False,
                         "updates_per_s": sum(nxs) * c["Q"] * 3 * steps / wall,
-                        "paper_single_core_s_per_run": paper_s if steps == c["steps"] else None})
+                        # per run at the paper's step count (scaled per step when the timed run is shorter)
+                        "s_per_run_at_paper_steps": wall / len(systems) * c["steps"] / steps,
+                        "paper_steps": c["steps"],
+                        "paper_single_core_s_per_run": paper_s})
             del s, f
     return out
 
@@ -341,19 +400,21 @@ def adjoint_ratio(E, torch, dev, nsteps):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=None, help="timed RK3 steps (default: the workload's 20000)")
-    ap.add_argument("--warmup", type=int, default=200)
-    ap.add_argument("--exec-mode", type=int, default=None, help="1 per stage, 2 persistent (default: autotune)")
-    ap.add_argument("--tile", type=int, default=None, help="16, 63 or 64 (default: autotune)")
+    ap.add_argument("--steps", type=int, default=20, help="timed RK3 steps of the 2D headline workload")
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--slab-steps", type=int, default=20000, help="timed RK3 steps of the slab workload")
+    ap.add_argument("--slab-warmup", type=int, default=200)
+    ap.add_argument("--exec-mode", type=int, default=None, help="slab: 1 per stage, 2 persistent (default: autotune)")
+    ap.add_argument("--tile", type=int, default=None, help="slab: 16, 63 or 64 (default: autotune)")
     ap.add_argument("--batch-steps", type=int, default=100)
+    ap.add_argument("--no-slab", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
-    ap.add_argument("--no-2d", action="store_true")
-    ap.add_argument("--paper-runs", action="store_true",
-                    help="also time the paper's own Sec. III B / III C runs at its parameters (about a minute)")
-    ap.add_argument("--paper-3b-steps", type=int, default=None, help="shorten the Sec. III B runs (default: 1e6)")
-    ap.add_argument("--steps-2d", type=int, default=10)
+    ap.add_argument("--no-paper-runs", action="store_true")
+    ap.add_argument("--paper-3b-steps", type=int, default=20000,
+                    help="steps of the Sec. III B runs (the paper's 1e6 take about 20 s; the default times "
+                         "20000 and scales per step)")
     ap.add_argument("--adjoint-steps", type=int, default=2000)
     ap.add_argument("--no-graph", action="store_true",
                     help="launch per-stage kernels one by one instead of replaying a captured HIP graph")
@@ -367,38 +428,49 @@ def main():
               "not implemented. Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
+    # the CPU baseline forks its workers before anything touches the GPU
+    cpu = None if args.no_cpu_baseline else cpu_baseline_2d()
+
     import torch
     import workloads
     from paper_2503_15187_amd import evlb as E
 
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
-    c, n, u, T = workloads.slab_1d()
-    steps = args.steps if args.steps is not None else c["steps"]
-    mode, tile = args.exec_mode, args.tile
-    if args.no_autotune:
-        mode, tile = E.EVLB_EXEC_PER_STAGE, default_tile(c["nx"])
-    m = measure(E, torch, dev, c["Q"], c["dx"], c["dt"], c["nx"], n, u, T, steps, args.warmup, mode, tile,
-                graph=not args.no_graph)
+    head = measure_2d(E, torch, dev, args.steps, args.warmup)
     out = {
         "metric": "site-velocity updates/s per RK stage (FP64)",
-        "value": m["value"],
+        "value": head["value"],
         "unit": "updates/s",
         "n_gpus": 1,
-        "steps": steps,
+        "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": m["ms_per_step"],
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "slab_evaporation_1d", "nx": c["nx"], "q": c["Q"], "dx": c["dx"],
-                   "dt": c["dt"], "T": c["T"], "exec": m["exec"], "tile_nodes": m["tile_nodes"]},
-        "roofline": dict(m["roofline"], traffic=measured_traffic("slab_evaporation_1d", m["roofline"]["kernel"])),
-        "hbm_peak_frac": m["roofline"]["frac"],
-        "wall_s": m["wall_s"],
+        "config": head["config"],
+        "roofline": head["roofline"],
+        "hbm_peak_frac": head["roofline"]["frac"],
+        "secondary": [],
     }
+    if not args.no_slab:
+        c, n, u, T = workloads.slab_1d()
+        mode, tile = args.exec_mode, args.tile
+        if args.no_autotune:
+            mode, tile = E.EVLB_EXEC_PER_STAGE, default_tile(c["nx"])
+        m = measure(E, torch, dev, c["Q"], c["dx"], c["dt"], c["nx"], n, u, T, args.slab_steps, args.slab_warmup,
+                    mode, tile, graph=not args.no_graph)
+        ent = {"config": {"workload": "slab_evaporation_1d", "nx": c["nx"], "q": c["Q"], "dx": c["dx"],
+                          "dt": c["dt"], "T": c["T"], "exec": m["exec"], "tile_nodes": m["tile_nodes"]},
+               "steps": args.slab_steps, "value": m["value"], "unit": "updates/s", "ms_per_step": m["ms_per_step"],
+               "roofline": dict(m["roofline"], traffic=measured_traffic("slab_evaporation_1d",
+                                                                          m["roofline"]["kernel"]))}
+        if not args.no_cpu_baseline:
+            ent["cpu_baseline_1core"] = cpu_baseline(c, n, u, T)
+        out["secondary"].append(ent)
     if not args.no_batch:
         cb, systems = workloads.batched_sweep_1d()
         nb = np.concatenate([x[0] for x in systems])
@@ -409,17 +481,15 @@ def main():
             bmode, btile = E.EVLB_EXEC_PER_STAGE, default_tile(cb["nx_list"])
         mb = measure(E, torch, dev, cb["Q"], cb["dx"], cb["dt"], cb["nx_list"], nb, ub, Tb,
                      args.batch_steps, 5, bmode, btile, graph=not args.no_graph)
-        out["secondary"] = [{
+        out["secondary"].append({
             "config": {"workload": "batched_sweep_1d", "n_sys": cb["n_sys"], "n_tot": int(len(nb)), "q": cb["Q"],
                        "dx": cb["dx"], "exec": mb["exec"], "tile_nodes": mb["tile_nodes"]},
             "steps": args.batch_steps, "value": mb["value"], "unit": "updates/s", "ms_per_step": mb["ms_per_step"],
-            "roofline": dict(mb["roofline"], traffic=measured_traffic("batched_sweep_1d", mb["roofline"]["kernel"]))}]
-    if not args.no_2d:
-        out["secondary"] = out.get("secondary", []) + [measure_2d(E, torch, dev, args.steps_2d, 1)]
+            "roofline": dict(mb["roofline"], traffic=measured_traffic("batched_sweep_1d", mb["roofline"]["kernel"]))})
     if not args.no_adjoint:
-        out["secondary"] = out.get("secondary", []) + [adjoint_ratio(E, torch, dev, args.adjoint_steps)]
-    if args.paper_runs:
-        out["secondary"] = out.get("secondary", []) + paper_runs(E, torch, dev, args.paper_3b_steps)
+        out["secondary"].append(adjoint_ratio(E, torch, dev, args.adjoint_steps))
+    if not args.no_paper_runs:
+        out["secondary"] += paper_runs(E, torch, dev, args.paper_3b_steps)
     out["hbm_copy"] = copy_bandwidth(torch, dev)
     if args.calibrate_copy:
         x = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device=dev)
@@ -427,8 +497,8 @@ def main():
         y.copy_(x)
         torch.cuda.synchronize()
         del x, y
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(c, n, u, T)
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
 
 

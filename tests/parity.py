@@ -17,18 +17,19 @@ In the rows next to the outer ones the Hermite expansion of the
 equilibrium (and the Hermite-projected momentum derivative) sums terms
 larger than their result, so the rounding of both sides is larger there
 relative to the row's own values than in the plane measure; the row bar is
-stated per velocity set from measurements (ROW_BAR).
+stated from measurements (ROW_BAR).
 """
 import numpy as np
 
-# largest accepted row_rel for one step (or one right-hand side) per
-# velocity set (rows per plane family: 8, 16, 24 in 1D, 256 in 2D).
-# Measured floors of the FP64 summation-order differences on MI355X, over
-# every term mask, tile shape and the equilibrium, 1 and 10 steps: Q = 16
-# 6.8e-14, Q = 24 9.6e-12 (rows 4 and 19, next to the outer rows), 2D
-# 2.4e-12 (the J0 term alone).  The bar is a multiple of the floor and grows
-# with the step count like the plane bar.
-ROW_BAR = {8: 1e-11, 16: 1e-11, 24: 1e-10, 256: 1e-10}
+# largest accepted row_rel for one step (or one right-hand side), every
+# velocity set.  Measured floors of the FP64 summation-order differences on
+# MI355X, over every term mask, tile shape and the equilibrium, 1 and 10
+# steps: Q = 16 6.8e-14 at T = 0.53, up to 2.1e-11 after 3 steps over the
+# 512 batched systems (T down to 0.45, where the equilibrium's Hermite sum
+# cancels most in the outer rows); Q = 24 9.6e-12 (rows 4 and 19, next to
+# the outer rows); 2D 2.4e-12 (the J0 term alone).  The bar grows with the
+# step count like the plane bar.
+ROW_BAR = 1e-10
 
 
 def _fam(x, i):
@@ -69,12 +70,11 @@ def rel(got, ref):
     return plane_rel(got, ref)
 
 
-def check(got, ref, tol, steps=1, what=""):
-    """Asserts the plane bar `tol` and the row bar: the larger of `tol` and
-    the velocity set's ROW_BAR times the number of steps."""
+def check(got, ref, tol, steps=1, what="", row_tol=None):
+    """Asserts the plane bar `tol` and the row bar: `row_tol` if given,
+    else the larger of `tol` and ROW_BAR times the number of steps."""
     pr = plane_rel(got, ref)
-    nrows = rows_of(_fam(ref, 0)).shape[0]
-    rb = max(tol, ROW_BAR[nrows] * max(1, steps))
+    rb = row_tol if row_tol is not None else max(tol, ROW_BAR * max(1, steps))
     rr = row_errors(got, ref)
     assert pr < tol, f"{what}: plane error {pr:.3e} >= {tol:.1e}"
     worst = np.unravel_index(np.argmax(rr), rr.shape)

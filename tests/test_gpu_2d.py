@@ -144,6 +144,24 @@ def test_rhs_force_model_none_2d():
     check(L, [LF, LG], 1e-11)
 
 
+@pytest.mark.timeout(900)
+def test_100_steps_2d_small_periodic_grid():
+    """100 steps on a 24 x 20 periodic grid (shorter than the force
+    window, so the density and force windows wrap several times; ragged in
+    x against the 16-column strips) against the oracle."""
+    nx, ny, nsteps = 24, 20, 100
+    c, n, ux, uy, T = small_case(nx, ny)
+    tb = tables(c)
+    F, G = oracle_state(c, n, ux, uy, T, tb)
+    Fo, Go = step2d.run(F, G, tb, nsteps)
+    s = solver(c, nx, ny)
+    f = td(np.stack([F, G]))
+    s.step(f, nsteps)
+    assert s.status() == E.EVLB_OK
+    err, rerr = check(f.cpu().numpy(), [Fo, Go], 1e-11, steps=nsteps)
+    print(f"2D 100-step rel err {err:.3e}, per row {rerr:.3e}", flush=True)
+
+
 @pytest.mark.parametrize("nsteps", [1, 4])
 def test_steps_2d(nsteps):
     nx, ny = 72, 40

@@ -180,14 +180,14 @@ def test_slab_loss_gradients_match_complex_step():
 
 def test_full_size_adjoint_gradients_match_finite_differences():
     """Adjoint workload at full size (2048 nodes, dx = sigma/4, Q = 16, slab
-    at 0.85 T_c, flux node x = 128 sigma) over 400 steps: adjoint gradients
+    at 0.85 T_c, flux node x = 128 sigma) over its 2000 steps: adjoint gradients
     against finite differences of the GPU loss (central in phi_sigma and in a
     direction of the initial density; second-order backward in sigma, whose
     kernel has a node on the branch point |x' - x| = sigma, third order))."""
     c, n0, u0, T0 = workloads.slab_1d(name="adjoint_slab_1d")
     target = workloads.adjoint_target(c, n0)
     i_f = c["nx"] // 2 + int(round(c["x_flux"] / c["dx"]))
-    nsteps = 400
+    nsteps = c["steps"]
 
     def loss(phi=1.0, sigma=1.0, dn=None, grad=False):
         s = E.Solver(c["Q"], c["dx"], c["dt"], c["nx"], phi_sigma=phi, sigma=sigma, adjoint=1)

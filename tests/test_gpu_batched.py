@@ -101,10 +101,11 @@ def test_autotune_picks_a_working_shape():
     assert (mode, tile) in AT.CANDIDATES and sec > 0
 
 
-def test_full_batch_sampled_systems_match_oracle():
+@pytest.mark.timeout(900)
+def test_full_batch_all_systems_match_oracle():
     """All 512 systems (about 1.1M nodes) in the launch shape the bench uses
-    (column tiles, one kernel per stage); the three shortest and one longest
-    system are recomputed by the oracle."""
+    (column tiles, one kernel per stage), 3 steps; every system is
+    recomputed by the oracle."""
     c, systems, n, u, T = batch(None)
     nxs = c["nx_list"]
     s = E.Solver(c["Q"], c["dx"], c["dt"], nxs, exec_mode=1, tile_nodes=63)
@@ -113,13 +114,12 @@ def test_full_batch_sampled_systems_match_oracle():
     assert s.status() == 0
     got = f.cpu().numpy()
     offs = np.concatenate([[0], np.cumsum(nxs)])
-    order = np.argsort(nxs)
     tb = step1d.Tables(Params(Q=c["Q"], dx=c["dx"], dt=c["dt"]))
-    for i in list(order[:3]) + [order[-1]]:
+    for i in range(len(nxs)):
         ni, ui, Ti = systems[i]
         F, G = step1d.initial_state(ni, ui, Ti, tb)
         F, G = step1d.run(F, G, tb, 3)
-        check(got[:, :, offs[i]:offs[i + 1]], [F, G], 1e-11, what=repr((i, nxs[i])))
+        check(got[:, :, offs[i]:offs[i + 1]], [F, G], 1e-11, steps=3, what=repr((i, nxs[i])))
 
 
 def test_full_batch_per_system_mass_conservation():

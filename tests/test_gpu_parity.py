@@ -256,7 +256,7 @@ def test_phase_separation_1000_steps_match_oracle():
     s = solver(c)
     f = s.equilibrium(td(n), td(u), td(T))
     s.step(f, c["steps"])
-    err, rerr = check(f.cpu().numpy(), [F, G], 1e-8, steps=c["steps"])
+    err, rerr = check(f.cpu().numpy(), [F, G], 1e-8, row_tol=1e-8)
     print(f"1000-step rel err {err:.3e}, per row {rerr:.3e}", flush=True)
     assert s.status() == 0
 
@@ -328,6 +328,118 @@ def test_slab_full_size_ten_steps_match_oracle():
     f = s.equilibrium(td(n), td(u), td(T))
     s.step(f, 10)
     check(f.cpu().numpy(), [F, G], 1e-10)
+
+
+@pytest.mark.timeout(900)
+def test_slab_full_size_1000_steps_match_oracle():
+    """Slab-evaporation workload at full size (4096 nodes, Q = 24, the
+    bench's launch shape) over 1000 steps against the oracle: 1e-8."""
+    c, n, u, T = workloads.slab_1d()
+    tb = oracle_tables(c)
+    F, G = step1d.initial_state(n, u, T, tb)
+    F, G = step1d.run(F, G, tb, 1000)
+    s = solver(c)
+    f = s.equilibrium(td(n), td(u), td(T))
+    s.step(f, 1000)
+    err, rerr = check(f.cpu().numpy(), [F, G], 1e-8, row_tol=1e-8)
+    print(f"slab 1000-step rel err {err:.3e}, per row {rerr:.3e}", flush=True)
+    assert s.status() == 0
+
+
+@pytest.mark.timeout(900)
+def test_adjoint_workload_forward_1000_steps_match_oracle():
+    """The adjoint workload's forward step at its own parameters (2048
+    nodes, dx = sigma/4, Q = 16, slab at T = 0.85 T_c) over 1000 steps."""
+    c, n, u, T = workloads.slab_1d(name="adjoint_slab_1d")
+    tb = oracle_tables(c)
+    F, G = step1d.initial_state(n, u, T, tb)
+    F, G = step1d.run(F, G, tb, 1000)
+    s = solver(c)
+    f = s.equilibrium(td(n), td(u), td(T))
+    s.step(f, 1000)
+    err, rerr = check(f.cpu().numpy(), [F, G], 1e-8, row_tol=1e-8)
+    print(f"adjoint-slab 1000-step rel err {err:.3e}, per row {rerr:.3e}", flush=True)
+    assert s.status() == 0
+
+
+@pytest.mark.parametrize("force", [0, 1])
+@pytest.mark.parametrize("which", ["sec3b", "sec3c"])
+def test_paper_parameter_runs_match_oracle(which, force):
+    """The paper's own numerical parameters (Sec. III: dx = sigma/10,
+    dt = 5e-3, Q = 16, r_cut/dx = 50) on its own initial states: the four
+    phase-separation runs of eq:rho_init_takata (Sec. III B) or the four
+    evaporating slabs of eq:tan (Sec. III C), as one batch, EV1 or EV2;
+    1 and 20 steps against independent oracle runs."""
+    c, systems = workloads.paper_sec3b() if which == "sec3b" else workloads.paper_sec3c()
+    print(f"paper parameters {which} force={force}", flush=True)
+    nxs = [len(x[0]) for x in systems]
+    tb = oracle_tables(c, force_model=force)
+    s = solver(c, nx=nxs, force_model=force)
+    f = s.equilibrium(*[td(np.concatenate([x[k] for x in systems])) for k in range(3)])
+    s.step(f, 1)
+    got1 = f.cpu().numpy()
+    s.step(f, 19)
+    got20 = f.cpu().numpy()
+    assert s.status() == 0
+    offs = np.cumsum([0] + nxs)
+    for i, (n, u, T) in enumerate(systems):
+        F, G = step1d.initial_state(n, u, T, tb)
+        F1, G1 = step1d.rk3_step(F, G, tb)
+        F20, G20 = step1d.run(F1, G1, tb, 19)
+        sl = slice(offs[i], offs[i + 1])
+        check(got1[:, :, sl], [F1, G1], 1e-11, what=repr((which, i)))
+        check(got20[:, :, sl], [F20, G20], 1e-11, steps=20, what=repr((which, i)))
+
+
+def _ev1_ev2_density_gap(which, steps):
+    """Runs the paper's Sec. III B or III C batch with the EV1 and with the
+    EV2 force; returns max|n_EV1 - n_EV2| / max n_EV1 per run."""
+    c, systems = workloads.paper_sec3b() if which == "sec3b" else workloads.paper_sec3c()
+    nxs = [len(x[0]) for x in systems]
+    cat = [td(np.concatenate([x[k] for x in systems])) for k in range(3)]
+    dens = []
+    for force in (0, 1):
+        s = solver(c, nx=nxs, force_model=force)
+        f = s.equilibrium(*cat)
+        s.step(f, steps)
+        assert s.status() == 0
+        dens.append(s.moments(f)[0].cpu().numpy())
+    offs = np.cumsum([0] + nxs)
+    gap = []
+    for i in range(len(nxs)):
+        a, b = dens[0][offs[i]:offs[i + 1]], dens[1][offs[i]:offs[i + 1]]
+        gap.append(np.max(np.abs(a - b)) / np.max(a))
+    return c, np.array(gap)
+
+
+def test_ev1_and_ev2_agree_on_smooth_profiles():
+    """Sec. III B reports that the EV1 (eq:F1) and EV2 (eq:F2) forces give
+    matching profiles at t = 100 from the sinusoidal state of
+    eq:rho_init_takata, for the lowest and the highest temperature, because
+    the density gradients stay small; Sec. III C that on the evaporating slab
+    they agree at T = 0.74 and that EV2 departs at the lowest temperature,
+    where the interface is sharpest.  Both batches run with each force at the
+    paper's parameters (Sec. III B to t = 100, 20000 steps; Sec. III C to
+    t = 75, 15000 steps).  Bars: the paper's figures show the two curves
+    overlapping at plot resolution, taken as 3% of the largest density; the
+    gap must shrink as T rises towards T_c (smoother profiles), and on the
+    slab be larger at T = 0.6 than at T = 0.74.  Part of every gap is not
+    the gradient expansion: EV1's kernel is truncated at r_cut = 5 sigma, so
+    its attraction parameter is 0.4% below the untruncated a = 4 pi / 3 that
+    EV2 uses."""
+    c, gap_b = _ev1_ev2_density_gap("sec3b", 20000)
+    temps_b = [p[0] for p in c["pairs"]]
+    c, gap_c = _ev1_ev2_density_gap("sec3c", 15000)
+    temps_c = c["T"]
+    print("Sec. III B t = 100, EV1-EV2 density gap by T:",
+          ", ".join(f"{t}: {g:.2e}" for t, g in zip(temps_b, gap_b)), flush=True)
+    print("Sec. III C t = 75, EV1-EV2 density gap by T:",
+          ", ".join(f"{t}: {g:.2e}" for t, g in zip(temps_c, gap_c)), flush=True)
+    assert np.all(gap_b < 3e-2)
+    order = np.argsort(temps_b)
+    assert np.all(np.diff(gap_b[order]) < 0)          # smaller gap at higher T
+    assert gap_c[int(np.argmin(temps_c))] > gap_c[int(np.argmax(temps_c))]
+    assert gap_c[int(np.argmax(temps_c))] < 3e-2
 
 
 def test_nonfinite_state_is_reported():
