@@ -29,10 +29,13 @@
  *  - Node-field layout: d_n, d_u, d_T, d_q are [n_tot].
  *  - dim = 2 (a fluid homogeneous in z; the paper's 1D model extended along
  *    y, see evlb_params.dim): one periodic nx x ny system, n_tot = nx ny,
- *    q = 16 nodes per velocity component, d_f[2][q][q][ny][nx] with plane
- *    d q^2 + k q + l holding F (d = 0) or G (d = 1) at (p_x, p_y) =
- *    (p_k, p_l); F = int f dp_z, G = int p_z^2/2 f dp_z.  Vector node fields
- *    (u, q) are [2][n_tot] (x then y component).
+ *    q = 16 nodes per velocity component, node-major d_f[2][ny][nx][q][q]:
+ *    d_f[d][y][x][k][l] is F (d = 0) or G (d = 1) at node (x, y) and
+ *    velocity (p_x, p_y) = (p_k, p_l), the q^2 values of a node contiguous
+ *    (whole cache lines per node and velocity row); F = int f dp_z,
+ *    G = int p_z^2/2 f dp_z.  Node fields stay [n_tot] per component with
+ *    node index y nx + x; vector node fields (u, q) are [2][n_tot] (x then y
+ *    component).
  *  - Return value: EVLB_OK or a negative error code.  Argument errors are
  *    detected on the host before any device work is enqueued and leave all
  *    buffers untouched.  Device-detected errors (a non-positive or

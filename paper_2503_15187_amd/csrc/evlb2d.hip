@@ -9,22 +9,20 @@
 // of Sec. II A integrated along z.
 //
 // State d_f[2][16][16][ny][nx] (plane d*256 + k*16 + l, node fastest).  One
-// TVD-RK3 stage is three kernels:
+// TVD-RK3 stage is two kernels:
 //   fields_kernel  32 x 8 nodes per workgroup, density tile with the force
-//                  radius as halo in LDS: disc-averaged density, contact value
-//                  (eq:carnstar), force (antisymmetric cell pairs), transport
+//                  radius as halo in LDS: n, u, T, q from the raw velocity
+//                  sums, disc-averaged density, contact value (eq:carnstar),
+//                  force (antisymmetric cell pairs), transport
 //                  (eq:viscosity, eq:tau, eq:prandtl), 4th-order central
 //                  gradients of X = n^2 chi T, T and u along x and y.
-//   adv_kernel     one wavefront per strip of 58 columns x 128 rows of one
-//                  velocity plane, marching down the rows with register
-//                  rings; every WENO-5 face computed once from per-node
-//                  stencil terms that three faces share,
-//                  W = a f^n + b f^(s-1) + c Adv(f^(s-1)).
-//   vel_kernel     16 nodes per wavefront, lanes = (node, group g of four p_x
-//                  rows): d/dp_x as (Dp x I) on the f64 MFMA (the node's 16 x 16
-//                  velocity matrix is the B operand), d/dp_y as (I x Dp) on the
-//                  VALU, Hermite equilibrium, Shakhov and J1 terms,
-//                  f^(s) = W + c R, and the velocity moments of f^(s).
+//   fused_kernel   one workgroup per strip of 8 columns, distribution and
+//                  segment of rows, all 256 velocities: WENO-5 faces along y
+//                  from a ring of rows in registers and along x from the row
+//                  in LDS, (Dp x I) and (I x Dp) on the f64 MFMA, Hermite
+//                  equilibrium, Shakhov and J1 terms, f^(s) = a f^n +
+//                  b f^(s-1) + c L(f^(s-1)), and the raw velocity sums of
+//                  f^(s) for the next stage's fields.
 #include "evlb2d.h"
 
 #include <cmath>
@@ -103,38 +101,68 @@ __device__ __forceinline__ void finish_moments(const Raw& m, double* out6, long 
 }
 
 // ---------------------------------------------------------------------------
-// moments of a state (first stage of a step, evlb_moments)
+// moments of a state (first stage of a step, evlb_moments).  State layout:
+// distribution d, node i, velocity (k, l) at ((d ntot + i) V + Q k + l): the
+// 2 KiB of a node's distribution are contiguous, so one wavefront reads a
+// node with lane L taking the velocities L + 64 m.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void moments_kernel(Dev D, const double* __restrict__ f, double* __restrict__ out6,
-                                                      const double* __restrict__ vel, int stage_input) {
-  const long long node = (long long)blockIdx.x * 256 + threadIdx.x;
-  if (node >= D.ntot) return;
-  const long long N = D.ntot;
-  Raw m{0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-#pragma unroll 1
-  for (int k = 0; k < Q; ++k) {
-    const double pk = vel[k];
-#pragma unroll 4
-    for (int l = 0; l < Q; ++l) {
-      const double pl = vel[l];
-      const double F = f[(long long)(k * Q + l) * N + node];
-      const double G = f[(long long)(V + k * Q + l) * N + node];
-      const double p2 = pk * pk + pl * pl;
-      m.n += F;
-      m.jx += pk * F;
-      m.jy += pl * F;
-      m.pxx += pk * pk * F;
-      m.pxy += pk * pl * F;
-      m.pyy += pl * pl * F;
-      m.rx += pk * p2 * F;
-      m.ry += pl * p2 * F;
-      m.g0 += G;
-      m.hx += pk * G;
-      m.hy += pl * G;
-    }
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__device__ __forceinline__ Raw velocity_sums(const Dev& D, const double* __restrict__ f,
+                                             const double* __restrict__ vel, long long node, int lane) {
+  const double* F = f + node * V;
+  const double* G = f + (D.ntot + node) * V;
+  double a[11] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+  const double pl = vel[lane & 15];
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    const int v = lane + 64 * m;
+    const double pk = vel[v >> 4];
+    const double Fv = F[v], Gv = G[v];
+    const double p2 = pk * pk + pl * pl;
+    a[0] += Fv;
+    a[1] += pk * Fv;
+    a[2] += pl * Fv;
+    a[3] += pk * pk * Fv;
+    a[4] += pk * pl * Fv;
+    a[5] += pl * pl * Fv;
+    a[6] += pk * p2 * Fv;
+    a[7] += pl * p2 * Fv;
+    a[8] += Gv;
+    a[9] += pk * Gv;
+    a[10] += pl * Gv;
   }
-  // as the input of a stage, an isothermal run sees its fixed temperature
-  finish_moments(m, out6, N, node, D.status, stage_input ? D.T_iso : 0.0);
+#pragma unroll
+  for (int i = 0; i < 11; ++i) a[i] = wave_sum(a[i]);
+  return Raw{a[0], a[1], a[2], a[3], a[4], a[5], a[6], a[7], a[8], a[9], a[10]};
+}
+
+// n, u, T, q of a state (evlb_moments): T is the moment temperature; one
+// wavefront per node
+__global__ __launch_bounds__(256) void moments_kernel(Dev D, const double* __restrict__ f, double* __restrict__ out6,
+                                                      const double* __restrict__ vel) {
+  const long long node = (long long)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (node >= D.ntot) return;
+  const Raw m = velocity_sums(D, f, vel, node, threadIdx.x & 63);
+  if ((threadIdx.x & 63) == 0) finish_moments(m, out6, D.ntot, node, D.status, 0.0);
+}
+
+// raw velocity sums [11][ntot] of a state, the input of a stage's fields
+__global__ __launch_bounds__(256) void raw_sums_kernel(Dev D, const double* __restrict__ f, double* __restrict__ raw,
+                                                       const double* __restrict__ vel) {
+  const long long node = (long long)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (node >= D.ntot) return;
+  const Raw m = velocity_sums(D, f, vel, node, threadIdx.x & 63);
+  const long long N = D.ntot;
+  const double v[11] = {m.n, m.jx, m.jy, m.pxx, m.pxy, m.pyy, m.rx, m.ry, m.g0, m.hx, m.hy};
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int i = 0; i < 11; ++i)
+    if (lane == i) raw[i * N + node] = v[i];
 }
 
 // Hermite equilibrium of one velocity component at unit density:
@@ -146,36 +174,34 @@ __device__ __forceinline__ void hermite_coeffs(double u, double T, double* a) {
   for (int m = 1; m < Q - 1; ++m) a[m + 1] = u * a[m] + (double)m * (T - 1.0) * a[m - 1];
 }
 
+// one wavefront per node: lane L writes the velocities L + 64 m, i.e. the
+// rows k = L / 16 + 4 m of column l = L % 16
 __global__ __launch_bounds__(256) void equilibrium_kernel(Dev D, const double* __restrict__ n_in,
                                                           const double* __restrict__ u_in,
                                                           const double* __restrict__ T_in, double* __restrict__ f,
                                                           const double* __restrict__ meq) {
-  const long long node = (long long)blockIdx.x * 256 + threadIdx.x;
+  const long long node = (long long)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (node >= D.ntot) return;
+  const int lane = threadIdx.x & 63, l = lane & 15;
   const long long N = D.ntot;
   const double n = n_in[node], ux = u_in[node], uy = u_in[N + node], T = T_in[node];
-  double ax[Q], ay[Q], ey[Q];
+  double ax[Q], ay[Q];
   hermite_coeffs(ux, T, ax);
   hermite_coeffs(uy, T, ay);
+  double ey = 0.0;
 #pragma unroll
-  for (int l = 0; l < Q; ++l) {
-    double s = 0.0;
+  for (int m = 0; m < Q; ++m) ey += meq[l * Q + m] * ay[m];
+  double* F = f + node * V;
+  double* G = f + (N + node) * V;
 #pragma unroll
-    for (int m = 0; m < Q; ++m) s += meq[l * Q + m] * ay[m];
-    ey[l] = s;
-  }
-#pragma unroll 1
-  for (int k = 0; k < Q; ++k) {
+  for (int mm = 0; mm < 4; ++mm) {
+    const int k = (lane >> 4) + 4 * mm;
     double ex = 0.0;
 #pragma unroll
     for (int m = 0; m < Q; ++m) ex += meq[k * Q + m] * ax[m];
-    const double nex = n * ex;
-#pragma unroll
-    for (int l = 0; l < Q; ++l) {
-      const double E = nex * ey[l];
-      f[(long long)(k * Q + l) * N + node] = E;
-      f[(long long)(V + k * Q + l) * N + node] = 0.5 * T * E;
-    }
+    const double E = n * ex * ey;
+    F[lane + 64 * mm] = E;
+    G[lane + 64 * mm] = 0.5 * T * E;
   }
 }
 
@@ -185,7 +211,18 @@ __global__ __launch_bounds__(256) void equilibrium_kernel(Dev D, const double* _
 constexpr int FTX = 32, FTY = 8, FNT = FTX * FTY;
 constexpr int GX = FTX + 4, GY = FTY + 4;  // tile +-2 (gradient stencil)
 
-__global__ __launch_bounds__(FNT) void fields_kernel(Dev D, const double* __restrict__ mom, double* __restrict__ fld,
+// u_x, u_y and T from the raw sums of a node (3/2 n T = sum |xi|^2/2 F + G);
+// an isothermal run sees its fixed temperature
+__device__ __forceinline__ void flow_of(const double* __restrict__ raw, long long N, long long node, double T_iso,
+                                        double& ux, double& uy, double& T) {
+  const double n = raw[node];
+  ux = raw[N + node] / n;
+  uy = raw[2 * N + node] / n;
+  const double e = 0.5 * (raw[3 * N + node] + raw[5 * N + node]) + raw[8 * N + node];
+  T = T_iso > 0.0 ? T_iso : (2.0 / 3.0) * (e - 0.5 * n * (ux * ux + uy * uy)) / n;
+}
+
+__global__ __launch_bounds__(FNT) void fields_kernel(Dev D, const double* __restrict__ raw, double* __restrict__ fld,
                                                      const int* __restrict__ avg_ofs,
                                                      const double* __restrict__ avg_w,
                                                      const int* __restrict__ pair_ofs,
@@ -207,14 +244,12 @@ __global__ __launch_bounds__(FNT) void fields_kernel(Dev D, const double* __rest
   const long long N = D.ntot;
   for (int i = tid; i < PX * PY; i += FNT) {
     const int r = i / PX, c = i - r * PX;
-    sn[i] = mom[(long long)wrap(y0 - H + r, D.ny) * D.nx + wrap(x0 - H + c, D.nx)];
+    sn[i] = raw[(long long)wrap(y0 - H + r, D.ny) * D.nx + wrap(x0 - H + c, D.nx)];
   }
   for (int i = tid; i < GX * GY; i += FNT) {
     const int r = i / GX, c = i - r * GX;
     const long long node = (long long)wrap(y0 - 2 + r, D.ny) * D.nx + wrap(x0 - 2 + c, D.nx);
-    sux[i] = mom[N + node];
-    suy[i] = mom[2 * N + node];
-    sT[i] = mom[3 * N + node];
+    flow_of(raw, N, node, D.T_iso, sux[i], suy[i], sT[i]);
   }
   __syncthreads();
   // averaged density over the disc, contact value, X on the tile +-2
@@ -283,473 +318,608 @@ __global__ __launch_bounds__(FNT) void fields_kernel(Dev D, const double* __rest
   const double Pr = (2.0 / 3.0) * (1.0 + 0.6 * yv) * (1.0 + 0.8 * yv + k12 * yv * yv) /
                     ((1.0 + 0.4 * yv) * (1.0 + 1.2 * yv + k32 * yv * yv));
   const double s = (1.0 - Pr) / (5.0 * n * T * T);
-  const double vals[NF] = {n, ux, uy, T, s * mom[4 * N + node], s * mom[5 * N + node], nu, -bn * chi, Fx, Fy,
+  // heat flux and the status check of this node from its raw sums
+  Raw m;
+  m.n = n;
+  m.jx = raw[N + node];
+  m.jy = raw[2 * N + node];
+  m.pxx = raw[3 * N + node];
+  m.pxy = raw[4 * N + node];
+  m.pyy = raw[5 * N + node];
+  m.rx = raw[6 * N + node];
+  m.ry = raw[7 * N + node];
+  m.g0 = raw[8 * N + node];
+  m.hx = raw[9 * N + node];
+  m.hy = raw[10 * N + node];
+  double q6[6];
+  finish_moments(m, q6, 1, 0, D.status, D.T_iso);
+  const double vals[NF] = {n, ux, uy, T, s * q6[4], s * q6[5], nu, -bn * chi, Fx, Fy,
                            Ax, Ay, Bx, By, Uxx, Uxy, Uyx, Uyy};
 #pragma unroll
   for (int i = 0; i < NF; ++i) fld[i * N + node] = vals[i];
 }
 
 // ---------------------------------------------------------------------------
-// advection: one wavefront per strip of 58 columns x AR rows of one plane
+// fused stage: one workgroup of sixteen wavefronts owns a strip of 8
+// columns, one distribution (F or G) and all 256 velocities, and marches
+// down a segment of rows
 // ---------------------------------------------------------------------------
-// WENO-5 (Jiang & Shu) rewritten around stencil centres.  A face between
-// v2 and v3 (v0 .. v4 ordered from the upwind side) combines three
-// candidate parabolas on the triples (v0 v1 v2), (v1 v2 v3), (v2 v3 v4).  In
-// terms of one triple (a, m, b), a on the upwind side, with c = a - 2m + b and
-// g = b - a, the candidate value and four times the smoothness indicator in
-// each of the three roles are
-//   role p (far upwind):  m + 13c/12 + 3g/4,  13c^2/3 + (2c + g)^2
-//   role 0 (centred):     m +   c/12 +  g/4,  13c^2/3 + g^2
-//   role m (downwind):    m +   c/12 -  g/4,  13c^2/3 + (2c - g)^2
-// so every node computes its triple once and three faces share it.  The
-// nonlinear weights 0.1, 0.6, 0.3 over (eps + beta_k)^2 are taken over the
-// common denominator; scaling every beta by 4 and eps with it multiplies all
-// three weights by the same 256, which cancels.  The division is a hardware
-// reciprocal refined by two Newton steps r <- r (2 - d r).
+// Thread (wavefront w, lane L): column c = L & 7 of the strip and r = L >> 3;
+// it holds the two velocities (k, l) = (w, r) and (w, r + 8).  In the
+// node-major state a wavefront's 16 velocities of a node are one 128-byte
+// line, read as two halves by consecutive loads.  Every wavefront sees one
+// sign of p_k (k < 8: p_k < 0) and every register slot one sign of p_l, so
+// both upwind choices are uniform.
 //
-// Lane t holds column x0 - 3 + t and marches down 128 rows.  Along y the
-// triples of rows y - 1 .. y + 2 and the raw rows y .. y + 3 sit in rings of
-// four registers indexed by row mod 4; the loop is unrolled by four so that
-// every ring index is a constant.  Along x each lane builds the triple of its
-// own column from its neighbours' row values and fetches the two triples it
-// lacks from the lanes that own them; the face on its right comes from lane
-// t + 1.  Lanes 3 .. 60 produce the 58 outputs.  No LDS, no barrier.
-constexpr int AW = 58;   // output columns per wavefront
-constexpr int AR = 128;  // output rows per wavefront (a multiple of 4)
-constexpr int ANT = 256; // four strips per workgroup
+// One barrier per row.  Iteration y is
+//  pre(y)   (each wavefront on its own 16 velocities, no data of another
+//           wavefront): the row to LDS with three halo columns each side;
+//           WENO-5 faces along y from a ring of five rows per velocity in
+//           registers; WENO-5 faces along x from the LDS row (each lane the
+//           face on its left, the one on its right from the next lane by
+//           DPP); (I x Dp) f on the f64 MFMA; the Shakhov + J1 collision
+//           terms as a polynomial in xi_x and xi_y per node; everything but
+//           the (Dp x I) f term and the strip-edge face folded into acc(y).
+//  barrier
+//  post(y)  the work that reads other wavefronts' rows or writes what they
+//           read: f^(s) of row y - 1 from acc(y - 1), the (Dp x I) f term and
+//           the strip-edge face of row y - 1, its store and its per-wavefront
+//           velocity sums (each lane one weighted term of the raw sums);
+//           wavefront 0 the raw velocity sums of row y - 2, 1 the Hermite
+//           coefficients a_m(u, T) of row y + 3, 2 the expansions e_k(u_x),
+//           e_l(u_y) of row y + 2 (one MFMA chain over 8 nodes x 2 axes), 3
+//           the per-node collision coefficients of row y + 3, 4 - 11
+//           (Dp x I) f of row y (v_mfma_f64_16x16x4 takes B element [c][col]
+//           from lane col + 16 c and returns row 4 j + c, column col in
+//           register j of that lane; col = (column, l parity)), 12 - 15 the
+//           strip-edge faces of row y.
+// What one wavefront writes and another reads crosses exactly one barrier,
+// and every such buffer is double (quadruple for the collision
+// coefficients, read a full iteration after they are written), so that a
+// wavefront one half-iteration ahead never overwrites what a slower one
+// still reads.  The ring's next row, f^n and the halo columns of the next
+// row and the node fields of row y + 4 are in flight across an iteration.
+constexpr int SW = 8;            // columns per strip
+constexpr int SNW = 16;          // wavefronts per workgroup
+constexpr int SNT = 64 * SNW;    // threads per workgroup
+constexpr int NRAW = 11;         // raw velocity sums per node: 8 of F, 3 of G
+// LDS strides (doubles).  A lane (c, r) reads plane r + 8 j at column c + i:
+// a plane stride of 8 (mod 16) puts the 16 lanes of one LDS pass, and of 32
+// lanes, on distinct banks.
+constexpr int TS = 24;                 // T: columns x0 - 3 .. x0 + 10 at 0 .. 13, (I x Dp) f at 14 .. 21,
+                                       // the strip-edge face of rows of parity 0 / 1 at 22 / 23
+constexpr int FIS = 16 * SW + 3 * 16;  // FI per k: 16 l x 8 interior columns, then 16 l x 3 right halo columns
+// per-node coefficients of the collision terms: the row polynomial
+//   nu f^S + J1 = tf n e_k e_l (P0 + xi_y (P1 + xi_y (P2 + P3 xi_y)))
+// with P0 = c0 + xi_x (c1 + xi_x (c2 + c3 xi_x)), P1 = d0 + xi_x (d1 + d2 xi_x),
+// P2 = e0 + c3 xi_x, P3 = d2 (a rearrangement of the reduced Shakhov and J1
+// terms), plus u_x, u_y, tf n, nu, F_x, F_y
+enum { CF_C0, CF_C1, CF_C2, CF_C3, CF_D0, CF_D1, CF_D2, CF_E0, CF_UX, CF_UY, CF_TFN, CF_NU, CF_FX, CF_FY, NCF };
 
-struct AdvArgs {
-  const double* fs;  // f^(s-1)
-  const double* f0;  // f^n
-  double* W;         // a f^n + b f^(s-1) + c Adv(f^(s-1)); may alias f0
-  double a, b, c;
-  int first;         // f0 == fs
+struct FusedArgs {
+  const double* fs;   // f^(s-1)
+  const double* f0;   // f^n (not read when first)
+  double* out;        // f^(s); may alias f0 (read pointwise before the write)
+  const double* fld;  // node fields [NF][ntot]
+  double* raw;        // raw velocity sums of f^(s) [NRAW][ntot] (want_mom)
+  double a, b, c;     // f^(s) = a f^n + b f^(s-1) + c L(f^(s-1))
+  int first, want_mom;
+  int nstrip, seglen;
 };
 
-struct Tri {
-  double bp, b0, bm;  // 4 beta in the roles p, 0, m
-  double qp, q0, qm;  // candidate values in the roles p, 0, m
+struct FusedSmem {
+  double T[V * TS];             // wavefront w's row, velocity (w, l) at 16 w + l (its own)
+  double FI[2][Q][FIS];         // row y: [k][8 l + (c ^ ((l >> 1) & 7))] interior (the swizzle spreads a
+                                // column of 16 l over the banks), [k][128 + 3 l + h] columns x0 + 8 + h
+  double DX[2][Q][16 * SW];     // (Dp x I) f^(s-1) of row y: [k][8 (l ^ 2 (k & 1)) + c] (the swizzle
+                                // puts the MFMA result rows k and k + 1 on distinct banks)
+  double AH[2][Q][16];          // Hermite coefficients a_m(u, T) of a row, column (node, axis)
+  double EK[2][2][Q][SW];       // unit-density expansions e_k(u_x) (axis 0), e_l(u_y) (axis 1)
+  double CF[4][NCF][SW];        // per-node coefficients of the collision row polynomial
+  double fl[2][NF][SW];         // node fields of a row
+  double mred[2][SNW][8][SW];   // per-wavefront terms of the raw velocity sums of a row (fixed k)
+  double aop[4][64];            // MFMA A operands Dp[i][c + 4 b] at lane i + 16 c
+  double eop[4][64];            // MFMA A operands meq[i][c + 4 b] at lane i + 16 c
+  double vel[Q];
 };
+static_assert(sizeof(FusedSmem) <= 160 * 1024, "fused stage LDS exceeds 160 KiB");
 
-__device__ __forceinline__ Tri tri(double a, double m, double b) {
-  const double c = fma(-2.0, m, a + b);
-  const double g = b - a;
-  const double a4 = (13.0 / 3.0) * c * c;
-  const double u = fma(2.0, c, g), w = fma(2.0, c, -g);
-  const double h = fma(1.0 / 12.0, c, m);
-  Tri t;
-  t.bp = fma(u, u, a4);
-  t.b0 = fma(g, g, a4);
-  t.bm = fma(w, w, a4);
-  t.qp = fma(0.75, g, fma(13.0 / 12.0, c, m));
-  t.q0 = fma(0.25, g, h);
-  t.qm = fma(-0.25, g, h);
-  return t;
-}
-
-// Face value from the triple in role p (bp, qp), role 0 and role m; eps4 = 4 eps.
-__device__ __forceinline__ double face3(double bp, double qp, double b0, double q0, double bm, double qm,
-                                        double eps4) {
-  double t0 = eps4 + bp; t0 *= t0;
-  double t1 = eps4 + b0; t1 *= t1;
-  double t2 = eps4 + bm; t2 *= t2;
-  const double w0 = 0.1 * (t1 * t2), w1 = 0.6 * (t0 * t2), w2 = 0.3 * (t0 * t1);
-  const double num = fma(w2, qm, fma(w1, q0, w0 * qp));
+// WENO-5 (Jiang & Shu) value at a face from the five values v0 .. v4 ordered
+// from the upwind side (v2 is the node upwind of the face): candidates 6 q_r,
+// smoothness 12 beta_r = 13 a^2 + 3 b^2, weights d_r / (eps + beta_r)^2 over
+// their common denominator with 10 d = (1, 6, 3) (every factor cancels), the
+// division through a hardware reciprocal refined by two Newton steps.
+__device__ __forceinline__ double weno5(double v0, double v1, double v2, double v3, double v4, double eps12) {
+  const double q0 = fma(2.0, v0, fma(-7.0, v1, 11.0 * v2));
+  const double q1 = fma(5.0, v2, fma(2.0, v3, -v1));
+  const double q2 = fma(2.0, v2, fma(5.0, v3, -v4));
+  const double a0 = fma(-2.0, v1, v0 + v2), c0 = fma(-4.0, v1, fma(3.0, v2, v0));
+  const double a1 = fma(-2.0, v2, v1 + v3), c1 = v1 - v3;
+  const double a2 = fma(-2.0, v3, v2 + v4), c2 = fma(-4.0, v3, fma(3.0, v2, v4));
+  double t0 = eps12 + fma(13.0 * a0, a0, 3.0 * (c0 * c0));
+  double t1 = eps12 + fma(13.0 * a1, a1, 3.0 * (c1 * c1));
+  double t2 = eps12 + fma(13.0 * a2, a2, 3.0 * (c2 * c2));
+  t0 *= t0;
+  t1 *= t1;
+  t2 *= t2;
+  const double w0 = t1 * t2, w1 = 6.0 * (t0 * t2), w2 = 3.0 * (t0 * t1);
+  const double num = fma(w2, q2, fma(w1, q1, w0 * q0));
   const double den = w0 + w1 + w2;
   double r = __builtin_amdgcn_rcp(den);
   r = fma(r, fma(-den, r, 1.0), r);
   r = fma(r, fma(-den, r, 1.0), r);
-  return num * r;
+  return (num * r) * (1.0 / 6.0);
 }
 
-// Oriented triple centred on m with its neighbours lo (lower index) and hi.
-template <bool POS>
-__device__ __forceinline__ Tri tri_dir(double lo, double m, double hi) {
-  return POS ? tri(lo, m, hi) : tri(hi, m, lo);
+// Lane i of every 16-lane row takes lane i + 1's value (lane 15: 0).
+__device__ __forceinline__ double row_next(double v) {
+  const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)b, 0x101, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), 0x101, 0xf, 0xf, false);
+  return __builtin_bit_cast(double, (unsigned long long)(unsigned)lo | ((unsigned long long)(unsigned)hi << 32));
 }
 
-struct AdvStrip {
-  const double* fs;   // this plane of f^(s-1)
-  const double* f0;   // this plane of f^n
-  double* W;          // this plane of W
-  int nx, ny, xc, yr, y0;
-  bool outcol;
-  double pxi, pyi, eps4;  // p_x / dx, p_y / dx
-  double rw[4];       // raw rows, slot = (row - y0) mod 4
-  Tri ct[4];          // triples of rows, slot = (row - y0) mod 4
-  double fyl;         // face between rows y - 1 and y
-  double nxr;         // row y + 3, loaded one row ahead
-  double f0n;         // f^n of row y, loaded one row ahead
-};
-
-// Row y = y0 + r with r = PH (mod 4): take row y + 3 (loaded one row ahead)
-// and load row y + 4, build the triple of row y + 2, the face between rows y
-// and y + 1, the two x faces of row y, update.
-template <bool PX, bool PY, int PH>
-__device__ __forceinline__ void adv_row(AdvStrip& S, const AdvArgs& A, int r) {
-  constexpr int s0 = PH & 3, s1 = (PH + 1) & 3, s2 = (PH + 2) & 3, s3 = (PH + 3) & 3;
-  S.rw[s3] = S.nxr;
-  S.nxr = S.fs[(long long)S.yr * S.nx + S.xc];
-  if (++S.yr == S.ny) S.yr = 0;
-  S.ct[s2] = tri_dir<PY>(S.rw[s1], S.rw[s2], S.rw[s3]);
-  // upwind below: triples of rows y - 1, y, y + 1; above: y + 2, y + 1, y
-  const double fyr = PY ? face3(S.ct[s3].bp, S.ct[s3].qp, S.ct[s0].b0, S.ct[s0].q0, S.ct[s1].bm, S.ct[s1].qm, S.eps4)
-                        : face3(S.ct[s2].bp, S.ct[s2].qp, S.ct[s1].b0, S.ct[s1].q0, S.ct[s0].bm, S.ct[s0].qm, S.eps4);
-  const double c0 = S.rw[s0];
-  const double m1 = __shfl_up(c0, 1), p1 = __shfl_down(c0, 1);
-  const Tri tx = tri_dir<PX>(m1, c0, p1);
-  double fxl;  // face between columns x - 1 and x
-  if (PX) {    // upwind left: triples of columns x - 2, x - 1, x
-    fxl = face3(__shfl_up(tx.bp, 2), __shfl_up(tx.qp, 2), __shfl_up(tx.b0, 1), __shfl_up(tx.q0, 1), tx.bm, tx.qm,
-                S.eps4);
-  } else {     // upwind right: triples of columns x + 1, x, x - 1
-    fxl = face3(__shfl_down(tx.bp, 1), __shfl_down(tx.qp, 1), tx.b0, tx.q0, __shfl_up(tx.bm, 1), __shfl_up(tx.qm, 1),
-                S.eps4);
-  }
-  const double fxr = __shfl_down(fxl, 1);
-  const int y = S.y0 + r;
-  const double f0v = A.first ? c0 : S.f0n;
-  // f^n of the next row of this strip (W may alias f^n: only rows this
-  // wavefront owns are read ahead)
-  if (!A.first && S.outcol && r + 1 < AR && y + 1 < S.ny) S.f0n = S.f0[(long long)(y + 1) * S.nx + S.xc];
-  if (S.outcol && y < S.ny) {
-    const long long node = (long long)y * S.nx + S.xc;
-    const double adv = fma(S.pxi, fxl - fxr, S.pyi * (S.fyl - fyr));
-    S.W[node] = fma(A.c, adv, fma(A.b, c0, A.a * f0v));
-  }
-  S.fyl = fyr;
+// Sum over the eight lanes of one column (lanes c + 8 r, r < 8), every lane
+// gets it: over the lanes i, i + 16, i + 32, i + 48 by the gfx950 cross-row
+// swaps of 16-lane rows and 32-lane halves, then over i and i ^ 8 by a DPP
+// rotation of each 16-lane row by 8.
+__device__ __forceinline__ double col8_sum(double v) {
+  const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+  const unsigned lo = (unsigned)b, hi = (unsigned)(b >> 32);
+  const auto l16 = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+  const auto h16 = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+  const double s = __builtin_bit_cast(double, (unsigned long long)l16[0] | ((unsigned long long)h16[0] << 32)) +
+                   __builtin_bit_cast(double, (unsigned long long)l16[1] | ((unsigned long long)h16[1] << 32));
+  const unsigned long long sb = __builtin_bit_cast(unsigned long long, s);
+  const unsigned slo = (unsigned)sb, shi = (unsigned)(sb >> 32);
+  const auto l32 = __builtin_amdgcn_permlane32_swap(slo, slo, false, false);
+  const auto h32 = __builtin_amdgcn_permlane32_swap(shi, shi, false, false);
+  const double t = __builtin_bit_cast(double, (unsigned long long)l32[0] | ((unsigned long long)h32[0] << 32)) +
+                   __builtin_bit_cast(double, (unsigned long long)l32[1] | ((unsigned long long)h32[1] << 32));
+  const unsigned long long tb = __builtin_bit_cast(unsigned long long, t);
+  const int rlo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)tb, 0x128, 0xf, 0xf, false);  // row_ror:8
+  const int rhi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(tb >> 32), 0x128, 0xf, 0xf, false);
+  return t + __builtin_bit_cast(double, (unsigned long long)(unsigned)rlo | ((unsigned long long)(unsigned)rhi << 32));
 }
 
-template <bool PX, bool PY>
-__device__ __forceinline__ void adv_strip(AdvStrip& S, const AdvArgs& A) {
-  // rows y0 - 3 .. y0 + 2: triples of rows y0 - 2 .. y0 + 1, raw rows y0 .. y0 + 2
-  double p[6];
-#pragma unroll
-  for (int i = 0; i < 6; ++i) {
-    p[i] = S.fs[(long long)S.yr * S.nx + S.xc];
-    if (++S.yr == S.ny) S.yr = 0;
-  }
-  S.ct[2] = tri_dir<PY>(p[0], p[1], p[2]);  // row y0 - 2
-  S.ct[3] = tri_dir<PY>(p[1], p[2], p[3]);  // row y0 - 1
-  S.ct[0] = tri_dir<PY>(p[2], p[3], p[4]);  // row y0
-  S.ct[1] = tri_dir<PY>(p[3], p[4], p[5]);  // row y0 + 1
-  S.rw[0] = p[3];
-  S.rw[1] = p[4];
-  S.rw[2] = p[5];
-  S.nxr = S.fs[(long long)S.yr * S.nx + S.xc];  // row y0 + 3
-  if (++S.yr == S.ny) S.yr = 0;
-  S.f0n = 0.0;
-  if (!A.first && S.outcol && S.y0 < S.ny) S.f0n = S.f0[(long long)S.y0 * S.nx + S.xc];
-  // face between rows y0 - 1 and y0
-  S.fyl = PY ? face3(S.ct[2].bp, S.ct[2].qp, S.ct[3].b0, S.ct[3].q0, S.ct[0].bm, S.ct[0].qm, S.eps4)
-             : face3(S.ct[1].bp, S.ct[1].qp, S.ct[0].b0, S.ct[0].q0, S.ct[3].bm, S.ct[3].qm, S.eps4);
-  for (int r = 0; r < AR; r += 4) {
-    adv_row<PX, PY, 0>(S, A, r);
-    adv_row<PX, PY, 1>(S, A, r + 1);
-    adv_row<PX, PY, 2>(S, A, r + 2);
-    adv_row<PX, PY, 3>(S, A, r + 3);
-  }
-}
-
-__global__ __launch_bounds__(ANT) void adv_kernel(Dev D, AdvArgs A, const double* __restrict__ vel) {
-  const int nsx = (D.nx + AW - 1) / AW, nsy = (D.ny + AR - 1) / AR;
-  // contiguous ranges of strips per XCD: neighbouring strips share its L2
-  const unsigned b = xcd_block(blockIdx.x, gridDim.x);
-  const unsigned wave = (unsigned)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-  const unsigned strip = b * 4u + wave;
-  const unsigned per_plane = (unsigned)nsx * (unsigned)nsy;
-  const int plane = (int)(strip / per_plane);
-  if (plane >= 2 * V) return;  // whole wavefront past the last strip
-  const unsigned sp = strip - (unsigned)plane * per_plane;
-  const int sy = (int)(sp / (unsigned)nsx), sx = (int)(sp - (unsigned)sy * (unsigned)nsx);
-  const int v = plane % V, k = v / Q, l = v - k * Q;
-  const double px = vel[k], py = vel[l];
-  const long long base = (long long)plane * D.ntot;
-  const int t = threadIdx.x & 63;
-  AdvStrip S;
-  S.fs = A.fs + base;
-  S.f0 = A.f0 + base;
-  S.W = A.W + base;
-  S.nx = D.nx;
-  S.ny = D.ny;
-  S.y0 = sy * AR;
-  const int x0 = sx * AW;
-  S.xc = wrap(x0 - 3 + t, D.nx);
-  S.yr = wrap(S.y0 - 3, D.ny);
-  S.outcol = t >= 3 && t < 3 + AW && x0 + t - 3 < D.nx;
-  S.pxi = px * D.inv_dx;
-  S.pyi = py * D.inv_dx;
-  S.eps4 = 4.0 * D.weno_eps;
-  if (px > 0.0) {
-    if (py > 0.0) adv_strip<true, true>(S, A);
-    else adv_strip<true, false>(S, A);
-  } else {
-    if (py > 0.0) adv_strip<false, true>(S, A);
-    else adv_strip<false, false>(S, A);
-  }
-}
-
-// W = a f^n + b f^(s-1) without advection (term tests)
-__global__ __launch_bounds__(256) void combine_kernel(Dev D, AdvArgs A) {
-  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
-  if (i >= 2 * V * D.ntot) return;
-  const double fv = A.fs[i];
-  const double f0v = A.first ? fv : A.f0[i];
-  A.W[i] = A.a * f0v + A.b * fv;
-}
-
-// ---------------------------------------------------------------------------
-// velocity space: 16 nodes per wavefront
-// ---------------------------------------------------------------------------
 typedef double dbl4 __attribute__((ext_vector_type(4)));
-typedef unsigned u32x2 __attribute__((__vector_size__(2 * sizeof(unsigned))));
 
-// Raw buffer access: a uniform base (SGPRs) plus a 32-bit per-lane byte
-// offset; an offset at or above num_records is out of range, so the store is
-// dropped (lanes past the row end) without a branch.
 constexpr int BUF_DWORD3 = 0x00020000;
-constexpr unsigned BUF_RANGE = 0x7fffffffu;
-constexpr unsigned BUF_OFF = 0xfffffff0u;  // out of range
 
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t buf(const double* base) {
-  return __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, (int)BUF_RANGE, BUF_DWORD3);
+  return __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, -1, BUF_DWORD3);
 }
-__device__ __forceinline__ double bload(const double* base, unsigned vo) {
-  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(buf(base), vo, 0, 0));
+__device__ __forceinline__ double bload(__amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, vo, so, 0));
 }
-__device__ __forceinline__ void bstore(double v, double* base, unsigned vo) {
-  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), buf(base), vo, 0, 0);
+typedef unsigned u32x2 __attribute__((__vector_size__(2 * sizeof(unsigned))));
+__device__ __forceinline__ void bstore(double v, __amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, vo, so, 0);
 }
 
-struct VelArgs {
-  const double* fs;   // f^(s-1)
-  double* W;          // in: advection part; out: f^(s) = W + c R(f^(s-1))
-  const double* fld;  // [NF][ntot]
-  double* mom;        // [6][ntot] moments of f^(s) (want_mom)
-  double c;
-  int want_mom;
-};
+// Hermite coefficients a_0 .. a_15 of the unit-density expansion along one
+// axis at node (column c, axis): a_0 = 1, a_1 = u, a_{m+1} = u a_m +
+// m (T - 1) a_{m-1}, into AH[buf][m][c + 8 axis] (the B operand layout of the
+// expansion MFMA).
+__device__ __forceinline__ void fused_hermite(FusedSmem& S, int fb, int t) {
+  const int c = t & (SW - 1), axis = t >> 3;
+  const double u = S.fl[fb][axis == 0 ? F_UX : F_UY][c], Tm1 = S.fl[fb][F_T][c] - 1.0;
+  double* a = &S.AH[fb][0][t];
+  double a0 = 1.0, a1 = u;
+  a[0] = a0;
+  a[16] = a1;
+#pragma unroll
+  for (int m = 1; m < Q - 1; ++m) {
+    const double an = fma(u, a1, (double)m * Tm1 * a0);
+    a0 = a1;
+    a1 = an;
+    a[16 * (m + 1)] = an;
+  }
+}
 
-// Lane (nd, g) = (lane & 15, lane >> 4) owns node x = x_w + nd and the velocity
-// rows k = g + 4 j, j < 4, for every l: M[j][l] = f[k][l] (64 values).
-// (Dp x I) M on the MFMA (v_mfma_f64_16x16x4: A operand element [i][c] from
-// lane i + 16 c, B operand element [c][col] from lane col + 16 c, result
-// element [4 j + c][col] in register j of lane col + 16 c): D = sum_b A_b B_b
-// over b < 4 with A_b[i][c] = Dp[i][c + 4b] (lane holds Dp[nd][g + 4b]) and
-// B_b[c][node] = M_node[c + 4b][l] (lane holds M[b][l]); D[k][node] comes back
-// as D[g + 4j][nd] in register j, the rows the lane owns.  (I x Dp) M
-// contracts over l, which the lane holds whole: VALU.
-//
-// Collision terms.  With xi = (xx, xy), th = |xi|^2 / T and the reduced
-// forms of the Shakhov and J1 terms (F: factor 1, th - 4; G: factor T/2,
-// th - 2), nu f^S + J1 = tf E P(xx, xy) with
-//   P = nu + pre (xx A_x + xy A_y) + (th - th0)(xx S_x + xy S_y + C)
-//       + 0.4 pre / T (xx^2 U_xx + xx xy (U_xy + U_yx) + xy^2 U_yy),
-//   S_x = nu s q_x + 0.3 pre B_x,  S_y = nu s q_y + 0.3 pre B_y,
-//   C = 0.2 pre div u,  pre = -b n chi.
-// For a fixed row (xx) P is a cubic in xy: alpha + xy (beta + xy (gamma +
-// delta xy)), set up once per row and pass.
-//
-// Occupancy: the unconstrained allocation takes about 300 registers (one
-// wavefront per SIMD); capped at 256 a few values spill to scratch, and the
-// second wavefront per SIMD hides more memory latency than the spills cost.
-template <bool FRC>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void vel_kernel(Dev D, VelArgs A, const double* __restrict__ vel,
-                                                  const double* __restrict__ meq,
-                                                  const double* __restrict__ dpm) {
-  __shared__ double s_ey[4][Q][16];  // per wave: e_l(u_y) of its 16 nodes (node fastest: no bank conflicts)
-  __shared__ double s_pc[4][4][4][64];  // per wave: row polynomial coefficients [al be ga ne][j][lane]
-  __shared__ double s_aop[4][64];       // MFMA A operands Dp[nd][g + 4 b] (the same for every wave)
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int nd = lane & 15, g = lane >> 4;
-  const int nseg = (D.nx + 63) >> 6;
-  const int y = blockIdx.x / nseg, seg = blockIdx.x - y * nseg;
-  const int x = seg * 64 + wave * 16 + nd;
-  const bool valid = x < D.nx;
-  const long long N = D.ntot;
-  // lanes past the row end work on the last node and store nothing
-  const long long node = (long long)y * D.nx + (valid ? x : D.nx - 1);
+// Per-node coefficients of the collision row polynomial of one
+// distribution (d: F or G) from the node fields of column c (fl[fb]) into
+// CF[cb].
+__device__ __forceinline__ void fused_coeffs(const Dev& D, FusedSmem& S, int fb, int cb, int c, int d) {
+  const double* fl = &S.fl[fb][0][0];
+#define FL(i) fl[(i) * SW + c]
   const bool j0 = (D.term_mask & EVLB_TERM_J0) != 0;
   const bool j1 = (D.term_mask & EVLB_TERM_J1) != 0;
+  const double T = FL(F_T), invT = 1.0 / T;
+  const double nu = j0 ? FL(F_NU) : 0.0;
+  const double pre = j1 ? FL(F_PRE) : 0.0;
+  const double th0 = d == 0 ? 4.0 : 2.0;
+  const double Sx = fma(nu, FL(F_SQX), 0.3 * pre * FL(F_BX));
+  const double Sy = fma(nu, FL(F_SQY), 0.3 * pre * FL(F_BY));
+  const double C = 0.2 * pre * (FL(F_UXX) + FL(F_UYY));
+  const double W4 = 0.4 * pre * invT;
+  double* cf = &S.CF[cb][0][c];
+  cf[CF_C0 * SW] = fma(-th0, C, nu);
+  cf[CF_C1 * SW] = fma(-th0, Sx, pre * FL(F_AX));
+  cf[CF_C2 * SW] = fma(invT, C, W4 * FL(F_UXX));
+  cf[CF_C3 * SW] = invT * Sx;
+  cf[CF_D0 * SW] = fma(-th0, Sy, pre * FL(F_AY));
+  cf[CF_D1 * SW] = W4 * (FL(F_UXY) + FL(F_UYX));
+  cf[CF_D2 * SW] = invT * Sy;
+  cf[CF_E0 * SW] = fma(invT, C, W4 * FL(F_UYY));
+  cf[CF_UX * SW] = FL(F_UX);
+  cf[CF_UY * SW] = FL(F_UY);
+  cf[CF_TFN * SW] = (j0 || j1) ? (d == 0 ? 1.0 : 0.5 * T) * FL(F_N) : 0.0;
+  cf[CF_NU * SW] = nu;
+  cf[CF_FX * SW] = FL(F_FX);
+  cf[CF_FY * SW] = FL(F_FY);
+#undef FL
+}
 
-  // unit-density Hermite equilibria: e_k(u_x) of the own rows in registers,
-  // e_l(u_y) shared by the four lanes of a node through LDS
-  double ex[4] = {0.0, 0.0, 0.0, 0.0};
-  {
-    const double ux = A.fld[F_UX * N + node], uy = A.fld[F_UY * N + node], T = A.fld[F_T * N + node];
-    double a[Q];
-    hermite_coeffs(uy, T, a);
+// e_k = sum_m meq[k][m] a_m for the 16 columns (node, axis) of a row on the
+// f64 MFMA (B element [c][col] = a_{c + 4 b}(col) from lane col + 16 c;
+// result e_{4 j + c}(col) in register j of that lane), into EK[buf].
+__device__ __forceinline__ void fused_expansions(FusedSmem& S, int fb, int L) {
+  const int c4 = L >> 4, col16 = L & 15;
+  dbl4 e = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      double s = 0.0;
+  for (int b = 0; b < 4; ++b)
+    e = __builtin_amdgcn_mfma_f64_16x16x4f64(S.eop[b][L], S.AH[fb][c4 + 4 * b][col16], e, 0, 0, 0);
 #pragma unroll
-      for (int m = 0; m < Q; ++m) s += meq[(g + 4 * i) * Q + m] * a[m];
-      s_ey[wave][g + 4 * i][nd] = s;
-    }
-    hermite_coeffs(ux, T, a);
+  for (int j = 0; j < 4; ++j) S.EK[fb][col16 >> 3][4 * j + c4][col16 & 7] = e[j];
+}
+
+// The term of raw velocity sum s contributed by one k from the sums
+// M_i = sum_l p_l^i f over the wavefront's l (p = p_k):
+//   F: n: M0, j_x: p M0, j_y: M1, P_xx: p^2 M0, P_xy: p M1, P_yy: M2,
+//      r_x: p^3 M0 + p M2, r_y: p^2 M1 + M3;
+//   G: g0: M0, h_x: p M0, h_y: M1.
+// Term s is p^a1 M_i1 (+ p^(a1 - 2) M_(i1 + 2) for r_x, r_y); i1 and a1 are
+// read from 2-bit fields of constants, so that lanes with different s run
+// the same instructions.
+__device__ __forceinline__ double fused_sum_term(int d, int s, const double* m, double p) {
+  const int i1 = ((d == 0 ? 18704 : 16) >> (2 * s)) & 3;
+  const int a1 = ((d == 0 ? 45444 : 4) >> (2 * s)) & 3;
+  const double p2 = p * p;
+  const double w1 = ((a1 & 1) ? p : 1.0) * ((a1 & 2) ? p2 : 1.0);
+  const double mi = i1 == 0 ? m[0] : (i1 == 1 ? m[1] : (i1 == 2 ? m[2] : m[3]));
+  const double m2 = d == 0 && s >= 6 ? (s == 6 ? m[2] : m[3]) : 0.0;
+  return fma(s == 6 ? p : 1.0, m2, w1 * mi);
+}
+
+// Raw velocity sum s = t / SW of row y at column t % SW: the sum over the 16
+// wavefronts' terms.
+__device__ __forceinline__ void fused_raw_sum(const Dev& D, const FusedArgs& A, const FusedSmem& S, int d, int t,
+                                              int x0, int y) {
+  const int s = t / SW, cc = t & (SW - 1);
+  if (x0 + cc >= D.nx) return;
+  const double* m = &S.mred[y & 1][0][s][cc];
+  double v[4];
 #pragma unroll
-    for (int k = 0; k < Q; ++k) {
-      double s = 0.0;
+  for (int i = 0; i < 4; ++i) v[i] = m[i * 8 * SW];
 #pragma unroll
-      for (int m = 0; m < Q; ++m) s += meq[k * Q + m] * a[m];
-      if ((k & 3) == g) ex[k >> 2] = s;
-    }
+  for (int l = 4; l < SNW; ++l) v[l & 3] += m[l * 8 * SW];
+  A.raw[(long long)((d == 0 ? 0 : 8) + s) * D.ntot + (long long)y * D.nx + x0 + cc] = (v[0] + v[1]) + (v[2] + v[3]);
+}
+
+template <bool ADV, bool FRC, bool FIRST>
+__global__ __launch_bounds__(SNT) void fused_kernel(Dev D, FusedArgs A, const double* __restrict__ velg,
+                                                    const double* __restrict__ meqg,
+                                                    const double* __restrict__ dpmg) {
+  __shared__ FusedSmem S;
+  const int tid0 = threadIdx.x;
+  const int w = __builtin_amdgcn_readfirstlane(tid0 >> 6);
+  const int L0 = tid0 & 63;
+  const int nx = D.nx, ny = D.ny;
+  // workgroup -> (segment, strip, distribution); contiguous ranges per XCD
+  // put neighbouring strips, which share halo columns, on one L2
+  const unsigned per = 2u * (unsigned)A.nstrip;
+  const unsigned tb = xcd_block(blockIdx.x, gridDim.x);
+  const int seg = (int)(tb / per), rr = (int)(tb - (unsigned)seg * per);
+  const int strip = rr >> 1, d = rr & 1;
+  const int x0 = strip * SW;
+  const int ya = seg * A.seglen;
+  const int yb = min(ya + A.seglen, ny);
+  const double eps12 = 12.0 * D.weno_eps;
+
+  if (tid0 < 256) {
+    const int e = (tid0 & 15) * Q + ((tid0 >> 4) & 3) + 4 * (tid0 >> 6);
+    S.aop[tid0 >> 6][tid0 & 63] = dpmg[e];
+    S.eop[tid0 >> 6][tid0 & 63] = meqg[e];
   }
-  double pkv[4];
+  if (tid0 < Q) S.vel[tid0] = velg[tid0];
+
+  const long long dofs = (long long)d * V * D.ntot;
+  const __amdgpu_buffer_rsrc_t rs = buf(A.fs + dofs), r0 = buf((FIRST ? A.fs : A.f0) + dofs);
+  const __amdgpu_buffer_rsrc_t ro = buf(A.out + dofs), rf = buf(A.fld);
+  auto wrapx = [&](int x) { x %= nx; return x < 0 ? x + nx : x; };
+  // per-lane byte offset of velocity (w, r) at the lane's column; (w, r + 8)
+  // is 64 bytes further, a row nx V doubles further
+  const unsigned vo = ((unsigned)wrapx(x0 + (L0 & 7)) * (unsigned)V + 16u * (unsigned)w + (unsigned)(L0 >> 3)) * 8u;
+  constexpr unsigned pso = 8u * 8u;
+  const unsigned rowb = (unsigned)nx * (unsigned)V * 8u;
+  // the wavefront's halo, 16 velocities x 6 columns (a 128-byte line each):
+  // lane L takes l = L >> 2 of column x0 - 3, x0 - 2, x0 - 1, x0 + 8 for
+  // L & 3 = 0 .. 3, and l = (L & 31) >> 1 of column x0 + 9 + (L & 1) (lanes
+  // 32 - 63 repeat 0 - 31); each load still covers whole lines, and the LDS
+  // writes of a 16-lane pass fall on at least 8 banks
+  const unsigned hvoA = ((unsigned)wrapx((L0 & 3) < 3 ? x0 - 3 + (L0 & 3) : x0 + SW) * (unsigned)V +
+                         16u * (unsigned)w + (unsigned)(L0 >> 2)) * 8u;
+  const unsigned hvoB = ((unsigned)wrapx(x0 + SW + 1 + (L0 & 1)) * (unsigned)V + 16u * (unsigned)w +
+                         (unsigned)((L0 & 31) >> 1)) * 8u;
+  // node fields [NF][ntot]: thread t < NF SW loads field t / SW of column t % SW
+  const bool fthr = tid0 < NF * SW;
+  const unsigned fvo =
+      fthr ? ((unsigned)(tid0 / SW) * (unsigned)D.ntot + (unsigned)wrapx(x0 + (tid0 & (SW - 1)))) * 8u : 0u;
+  const unsigned rowf = (unsigned)nx * 8u;
+  const double pk = velg[w];
+  const double pxi = pk * D.inv_dx;
+  const bool PX = pk > 0.0;  // uniform per wavefront
+  const double bb = FIRST ? A.a + A.b : A.b;  // the first stage has f^n = f^(s-1)
+
+  // y within 4 rows of the domain (ny >= 8)
+  auto wrapy = [&](int y) { return (unsigned)(y < 0 ? y + ny : (y >= ny ? y - ny : y)); };
+  auto rowso = [&](int y) { return wrapy(y) * rowb; };
+  auto rowsf = [&](int y) { return wrapy(y) * rowf; };
+
+  // ---- prologue.  The ring R5[j] holds, per velocity, five consecutive
+  // rows in marching order: (y - 2 .. y + 2) for j = 1 (p_l > 0), (y - 1 ..
+  // y + 3) for j = 0 (p_l < 0), so that the face between rows y and y + 1 is
+  // weno5(R0 .. R4), resp. weno5(R4 .. R0), and the row dropped after the
+  // face is always R0.
+  double R5[2][5];
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    pkv[j] = vel[g + 4 * j];
-    if (wave == 0) s_aop[j][lane] = dpm[nd * Q + g + 4 * j];
+  for (int i = 0; i < 5; ++i) {
+#pragma unroll
+    for (int j = 0; j < 2; ++j) R5[j][i] = bload(rs, vo, j * pso + rowso(ya - 1 - j + i));
+  }
+  double fyl[2] = {0.0, 0.0};
+  if (ADV) {  // the face between rows ya - 1 and ya
+    const double e0 = bload(rs, vo, rowso(ya - 2)), e1 = bload(rs, vo, pso + rowso(ya - 3));
+    fyl[0] = weno5(R5[0][3], R5[0][2], R5[0][1], R5[0][0], e0, eps12);
+    fyl[1] = weno5(e1, R5[1][0], R5[1][1], R5[1][2], R5[1][3], eps12);
+  }
+  // f^n and the halo of row ya, node fields of rows ya .. ya + 3
+  double f0v[2] = {0.0, 0.0}, hv[2];
+  if (!FIRST) {
+#pragma unroll
+    for (int j = 0; j < 2; ++j) f0v[j] = bload(r0, vo, j * pso + rowso(ya));
+  }
+  hv[0] = bload(rs, hvoA, rowso(ya));
+  hv[1] = bload(rs, hvoB, rowso(ya));
+  double fq = bload(rf, fvo, rowsf(ya + 3));
+  const double fq2 = bload(rf, fvo, rowsf(ya + 2));
+  if (fthr) {
+    S.fl[ya & 1][tid0 / SW][tid0 & (SW - 1)] = bload(rf, fvo, rowsf(ya));
+    S.fl[(ya + 1) & 1][tid0 / SW][tid0 & (SW - 1)] = bload(rf, fvo, rowsf(ya + 1));
   }
   __syncthreads();
-  const double* eyv = &s_ey[wave][0][nd];  // e_l at eyv[16 l]
+  // Hermite and collision coefficients of rows ya, ya + 1
+  if (w == 1 && L0 < 32) fused_hermite(S, (ya + (L0 >> 4)) & 1, L0 & 15);
+  if (w == 3 && L0 < 16) fused_coeffs(D, S, (ya + (L0 >> 3)) & 1, (ya + (L0 >> 3)) & 3, L0 & 7, d);
+  __syncthreads();
+  // their expansions; the node fields of row ya + 2 replace those of row ya
+  if (w == 1) fused_expansions(S, ya & 1, L0);
+  if (w == 2) fused_expansions(S, (ya + 1) & 1, L0);
+  if (fthr) S.fl[ya & 1][tid0 / SW][tid0 & (SW - 1)] = fq2;
+  __syncthreads();
+  if (w == 1 && L0 < 16) fused_hermite(S, ya & 1, L0);
+  if (w == 3 && L0 < 8) fused_coeffs(D, S, ya & 1, (ya + 2) & 3, L0, d);
+  __syncthreads();
 
-  // per-lane byte offset of (row g, node) from a plane base; < 2^31 by the
-  // node-count limit of the 2D path
-  const unsigned vo = (unsigned)(((long long)g * Q * N + node) * 8);
-  const unsigned vs = valid ? vo : BUF_OFF;
-  Raw m{0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-#pragma unroll 1
-  for (int d = 0; d < 2; ++d) {
-    // Opaque copies: what the F and G passes share (Dp rows, plane bases,
-    // node fields) is recomputed in each pass instead of being hoisted out of
-    // the loop and held live across both.
-    long long Nd = N;
-    int z = 0;  // an opaque zero keeps the pointers' address space and uniformity
-    asm volatile("" : "+s"(Nd), "+s"(z));
-    const double* dp = dpm + z;
-    const double* vl = vel + z;
-    const double* fd = A.fld + z;
-    const double* fsd = A.fs + (long long)d * V * Nd;
-    double* wd = A.W + (long long)d * V * Nd;
-    // plane of own row j (k = g + 4 j) and column l, relative to row g
-#define PLANE(base, j, l) ((base) + (long long)(4 * (j) * Q + (l)) * Nd)
-    double M[4][Q];
+  const int nsum = d == 0 ? 8 : 3;
+  double accP[2] = {0.0, 0.0}, cfxP = 0.0;  // acc and c F_x of the row before
+  for (int y = ya; y <= yb; ++y) {
+    // Opaque per-row copies of the thread indices: every LDS address and
+    // table value below is derived from them inside the row, so that the
+    // compiler does not hoist them out of the loop and hold (or spill) them
+    // across it.
+    int tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
+    const int L = tid & 63, col = L & (SW - 1), r = L >> 3;
+    const int yp = y & 1;
+    double accN[2] = {0.0, 0.0}, cfxN = 0.0;
+    // ---------------- pre(y) ----------------
+    if (y < yb) {
+      if (y > ya) {
+        // advance the ring: the row loaded into R0 last row moves to the end
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
-#pragma unroll
-      for (int l = 0; l < Q; ++l) M[j][l] = bload(PLANE(fsd, j, l), vo);
-    // W of column l is loaded PF columns ahead of its use
-    constexpr int PF = 1;
-    double wb[PF][4];
-#pragma unroll
-    for (int p = 0; p < PF; ++p)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) wb[p][j] = bload(PLANE(wd, j, p), vo);
-
-    // row polynomials of the collision terms
-    // the row polynomials live in LDS (registers are the occupancy limit)
-    double(*pc)[4][64] = s_pc[wave];
-    double de, nu, Fx, Fy, uy;
-    {
-      const double n = fd[F_N * Nd + node], ux = fd[F_UX * Nd + node], T = fd[F_T * Nd + node];
-      uy = fd[F_UY * Nd + node];
-      const double nu0 = fd[F_NU * Nd + node];
-      nu = j0 ? nu0 : 0.0;
-      const double pre = j1 ? fd[F_PRE * Nd + node] : 0.0;
-      Fx = fd[F_FX * Nd + node];
-      Fy = fd[F_FY * Nd + node];
-      const double invT = 1.0 / T;
-      const double tf = d == 0 ? 1.0 : 0.5 * T;
-      const double th0 = d == 0 ? 4.0 : 2.0;
-      const double uxx = fd[F_UXX * Nd + node], uyy = fd[F_UYY * Nd + node];
-      const double Sx = nu * fd[F_SQX * Nd + node] + 0.3 * pre * fd[F_BX * Nd + node];
-      const double Sy = nu * fd[F_SQY * Nd + node] + 0.3 * pre * fd[F_BY * Nd + node];
-      const double C = 0.2 * pre * (uxx + uyy);
-      const double W4 = 0.4 * pre * invT;
-      const double pAx = pre * fd[F_AX * Nd + node], pAy = pre * fd[F_AY * Nd + node];
-      const double Uc = W4 * (fd[F_UXY * Nd + node] + fd[F_UYX * Nd + node]);
-      de = invT * Sy;
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const double xx = pkv[j] - ux;
-        const double t0 = xx * xx * invT - th0;
-        const double r = xx * Sx + C;
-        pc[0][j][lane] = nu + pAx * xx + t0 * r + W4 * uxx * xx * xx;
-        pc[1][j][lane] = pAy + t0 * Sy + Uc * xx;
-        pc[2][j][lane] = invT * r + W4 * uyy;
-        pc[3][j][lane] = (j0 || j1) ? tf * n * ex[j] : 0.0;
-      }
-    }
-    // velocity sums of the new state: 1, p_x, p_y (both passes), p_x^2,
-    // p_x p_y, p_y^2, p_x |p|^2, p_y |p|^2 (used for F only)
-    double S[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    // fully unrolled: every M[j][l] index is static, M stays in registers
-#pragma unroll
-    for (int l = 0; l < Q; ++l) {
-      double wcur[4];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) wcur[j] = wb[l % PF][j];
-      if (l + PF < Q) {
-#pragma unroll
-        for (int j = 0; j < 4; ++j) wb[l % PF][j] = bload(PLANE(wd, j, l + PF), vo);
-      }
-      // an opaque copy of the lane index per column keeps the MFMA operands
-      // and polynomial coefficients in LDS instead of being hoisted back into
-      // registers
-      int pli = lane;
-      asm volatile("" : "+v"(pli));
-      dbl4 acc = {0.0, 0.0, 0.0, 0.0};
-      if (FRC) {
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(s_aop[0][pli], M[0][l], acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(s_aop[1][pli], M[1][l], acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(s_aop[2][pli], M[2][l], acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(s_aop[3][pli], M[3][l], acc, 0, 0, 0);
-      }
-      const double pl = vl[l];
-      const double xy = pl - uy;
-      const double eyl = eyv[16 * l];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        double R = pc[3][j][pli] * eyl * (pc[0][j][pli] + xy * (pc[1][j][pli] + xy * (pc[2][j][pli] + de * xy))) -
-                   nu * M[j][l];
-        if (FRC) {
-          double d0 = 0.0, d1 = 0.0;
-#pragma unroll
-          for (int l2 = 0; l2 < Q; l2 += 2) {
-            d0 += dp[l * Q + l2] * M[j][l2];
-            d1 += dp[l * Q + l2 + 1] * M[j][l2 + 1];
-          }
-          R -= Fx * acc[j] + Fy * (d0 + d1);
+        for (int j = 0; j < 2; ++j) {
+          const double t = R5[j][0];
+          R5[j][0] = R5[j][1];
+          R5[j][1] = R5[j][2];
+          R5[j][2] = R5[j][3];
+          R5[j][3] = R5[j][4];
+          R5[j][4] = t;
         }
-        const double out = wcur[j] + A.c * R;
-        bstore(out, PLANE(wd, j, l), vs);
-        const double pk = pkv[j];
-        const double a1 = pk * out, a2 = pl * out;
-        const double p2 = pk * pk + pl * pl;
-        S[0] += out;
-        S[1] += a1;
-        S[2] += a2;
-        S[3] += pk * a1;
-        S[4] += pl * a1;
-        S[5] += pl * a2;
-        S[6] += p2 * a1;
-        S[7] += p2 * a2;
       }
-      // one column at a time: keeps later columns' work from being hoisted
-      __builtin_amdgcn_sched_barrier(0);
+      double* Tw = &S.T[16 * w * TS];  // this wavefront's 16 velocities
+      double* fi = &S.FI[yp][w][0];
+      const double* cf = &S.CF[y & 3][0][col];
+      const double nu = cf[CF_NU * SW];
+      double cur[2], part[2], base[2];
+      cur[0] = R5[0][1];  // row y
+      cur[1] = R5[1][2];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        Tw[(r + 8 * j) * TS + 3 + col] = cur[j];
+        fi[8 * (r + 8 * j) + (col ^ (((r + 8 * j) >> 1) & 7))] = cur[j];
+        base[j] = fma(A.a, f0v[j], bb * cur[j]);
+        part[j] = -nu * cur[j];
+      }
+      {
+        const int lA = L >> 2, hA = L & 3, lB = (L & 31) >> 1, hB = 4 + (L & 1);
+        Tw[lA * TS + (hA < 3 ? hA : SW + hA)] = hv[0];
+        if (hA == 3) fi[16 * SW + 3 * lA] = hv[0];
+        Tw[lB * TS + SW + hB] = hv[1];
+        fi[16 * SW + 3 * lB + hB - 3] = hv[1];
+      }
+      if (tid < NF * SW) S.fl[(y + 3) & 1][tid / SW][tid & (SW - 1)] = fq;
+      if (ADV) {
+        // y faces: j = 0 upwind from above, j = 1 from below
+        const double fyr0 = weno5(R5[0][4], R5[0][3], R5[0][2], R5[0][1], R5[0][0], eps12);
+        const double fyr1 = weno5(R5[1][0], R5[1][1], R5[1][2], R5[1][3], R5[1][4], eps12);
+        part[0] = fma(D.inv_dx * S.vel[r], fyl[0] - fyr0, part[0]);
+        part[1] = fma(D.inv_dx * S.vel[r + 8], fyl[1] - fyr1, part[1]);
+        fyl[0] = fyr0;
+        fyl[1] = fyr1;
+      }
+      // in flight across the rest of this iteration: node fields of row
+      // y + 4 (issued first: the wait for it in the next iteration then
+      // leaves the later loads in flight), the ring's next row (into the slot
+      // just dropped), f^n and the halo of row y + 1 (unconditional, past the
+      // segment too: a load under a condition would make the compiler copy
+      // the register at the loop latch, which waits for every load in flight)
+      fq = bload(rf, fvo, rowsf(y + 4));
+#pragma unroll
+      for (int j = 0; j < 2; ++j) R5[j][0] = bload(rs, vo, j * pso + rowso(y + 4 - j));  // row (y + 1) + 3 - j
+      {
+        const unsigned so1 = rowso(y + 1);
+        if (!FIRST) {
+#pragma unroll
+          for (int j = 0; j < 2; ++j) f0v[j] = bload(r0, vo, j * pso + so1);
+        }
+        hv[0] = bload(rs, hvoA, so1);
+        hv[1] = bload(rs, hvoB, so1);
+      }
+      if (ADV) {
+        // x faces from this wavefront's LDS row: each lane the face on its
+        // left, the face on its right from the next lane (the last column:
+        // the strip-edge face, added in post(y + 1))
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          const double* t = &Tw[(r + 8 * j) * TS + col];
+          const double lf = PX ? weno5(t[0], t[1], t[2], t[3], t[4], eps12)
+                               : weno5(t[5], t[4], t[3], t[2], t[1], eps12);
+          // every lane runs the DPP move (a lane masked off would read as 0
+          // to its neighbour), then the last column drops what it read
+          const double nb = row_next(lf);
+          const double rf = col == SW - 1 ? 0.0 : nb;
+          part[j] = fma(pxi, lf - rf, part[j]);
+        }
+      }
+      double dy[2] = {0.0, 0.0};
+      if (FRC) {
+        // (I x Dp) f for k = w: B[c][col16] = f(w, l = c + 4 b) at column
+        // col16 & 7 (lanes with col16 >= 8 repeat columns 0 - 7); row l' =
+        // 4 j + c of the result from the lanes col16 < 8 to columns 14 - 21
+        const int c4 = L >> 4, c8 = L & 7;
+        dbl4 dd = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+          dd = __builtin_amdgcn_mfma_f64_16x16x4f64(S.aop[b][L], Tw[(c4 + 4 * b) * TS + 3 + c8], dd, 0, 0, 0);
+        if ((L & 8) == 0) {
+#pragma unroll
+          for (int j = 0; j < 4; ++j) Tw[(4 * j + c4) * TS + 14 + c8] = dd[j];
+        }
+#pragma unroll
+        for (int j = 0; j < 2; ++j) dy[j] = Tw[(r + 8 * j) * TS + 14 + col];
+      }
+      // collision terms: with xi_x = p_k - u_x fixed per wavefront, the row
+      // polynomial in xi_y = p_l - u_y
+      const double xx = pk - cf[CF_UX * SW];
+      const double c3 = cf[CF_C3 * SW], d2 = cf[CF_D2 * SW];
+      const double P0 = fma(xx, fma(xx, fma(c3, xx, cf[CF_C2 * SW]), cf[CF_C1 * SW]), cf[CF_C0 * SW]);
+      const double P1 = fma(xx, fma(d2, xx, cf[CF_D1 * SW]), cf[CF_D0 * SW]);
+      const double P2 = fma(c3, xx, cf[CF_E0 * SW]);
+      const double tfe = cf[CF_TFN * SW] * S.EK[yp][0][w][col];  // tf n e_k(u_x)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int l = r + 8 * j;
+        const double xy = S.vel[l] - cf[CF_UY * SW];
+        double Lc = tfe * S.EK[yp][1][l][col] * fma(xy, fma(xy, fma(d2, xy, P2), P1), P0);
+        if (FRC) Lc = fma(-cf[CF_FY * SW], dy[j], Lc);
+        accN[j] = fma(A.c, part[j] + Lc, base[j]);
+      }
+      if (FRC) cfxN = A.c * cf[CF_FX * SW];
     }
-#undef PLANE
-    if (d == 0) {
-      m.n = S[0]; m.jx = S[1]; m.jy = S[2]; m.pxx = S[3]; m.pxy = S[4]; m.pyy = S[5]; m.rx = S[6]; m.ry = S[7];
+    __syncthreads();
+    // ---------------- post(y) ----------------
+    if (y > ya) {
+      // f^(s) of row y - 1
+      const int pb = (y - 1) & 1;
+      const unsigned so = rowso(y - 1);
+      double sm[4] = {0, 0, 0, 0};
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int l = r + 8 * j;
+        const double plb = S.vel[l];
+        double o = accP[j];
+        if (FRC) o = fma(-cfxP, S.DX[pb][w][8 * (l ^ (2 * (w & 1))) + col], o);
+        if (ADV && col == SW - 1) o = fma(-A.c * pxi, S.T[(16 * w + l) * TS + 22 + pb], o);
+        if (x0 + col < nx) bstore(o, ro, vo, j * pso + so);
+        if (A.want_mom) {
+          // sums over l of p_l^i f^(s) for this wavefront's k (F: i < 4, G: i < 2)
+          const double a1 = plb * o;
+          sm[0] += o;
+          sm[1] += a1;
+          if (d == 0) {
+            const double a2 = plb * a1;
+            sm[2] += a2;
+            sm[3] += plb * a2;
+          }
+        }
+      }
+      if (A.want_mom) {
+        // every lane of the column gets M_0 .. M_3, lane r writes term r
+        double m[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+          if (s < (d == 0 ? 4 : 2)) m[s] = col8_sum(sm[s]);
+        const double t = fused_sum_term(d, r, m, pk);
+        if (r < nsum) S.mred[pb][w][r][col] = t;
+      }
+    }
+    // the serial chains on the oldest wavefront of four SIMDs (the arbiter
+    // issues the oldest first), the MFMA and WENO work one or two per SIMD
+    if (w == 0) {
+      if (A.want_mom && y - 2 >= ya && L < nsum * SW) fused_raw_sum(D, A, S, d, L, x0, y - 2);
+    } else if (w == 1) {
+      // Hermite coefficients of row y + 3
+      if (y + 3 < yb && L < 16) fused_hermite(S, (y + 3) & 1, L);
+    } else if (w == 2) {
+      if (y + 2 < yb) fused_expansions(S, (y + 2) & 1, L);
+    } else if (w == 3) {
+      // collision coefficients of row y + 3
+      if (y + 3 < yb && L < SW) fused_coeffs(D, S, (y + 3) & 1, (y + 3) & 3, L, d);
+    } else if (w < 12) {
+      if (FRC && y < yb) {
+        // (Dp x I) f for l = 2 (w - 4) + lh: B[c][col16] = f(k = c + 4 b, l),
+        // col16 = (column, lh)
+        const int c4 = L >> 4, lq = 2 * (w - 4) + ((L >> 3) & 1);
+        dbl4 dd = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+          dd = __builtin_amdgcn_mfma_f64_16x16x4f64(S.aop[b][L], S.FI[yp][c4 + 4 * b][8 * lq + (col ^ ((lq >> 1) & 7))],
+                                                    dd, 0, 0, 0);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int k = 4 * j + c4;
+          S.DX[yp][k][8 * (lq ^ (2 * (k & 1))) + col] = dd[j];
+        }
+      }
     } else {
-      m.g0 = S[0]; m.hx = S[1]; m.hy = S[2];
+      if (ADV && y < yb) {
+        // the strip-edge face of velocity (k, l), q = 16 k + l, from the
+        // interior columns 5 - 7 and the right halo of FI, into the owner's T
+        const int q = 64 * (w - 12) + L, k = q >> 4, l = q & 15;
+        const double* fi = &S.FI[yp][k][8 * l];
+        const int sw = (l >> 1) & 7;
+        const double i5 = fi[5 ^ sw], i6 = fi[6 ^ sw], i7 = fi[7 ^ sw];
+        fi = &S.FI[yp][k][0];
+        const double h0 = fi[16 * SW + 3 * l], h1 = fi[16 * SW + 3 * l + 1], h2 = fi[16 * SW + 3 * l + 2];
+        const bool px = k >= 8;
+        S.T[q * TS + 22 + yp] = weno5(px ? i5 : h2, px ? i6 : h1, px ? i7 : h0, px ? h0 : i7, px ? h1 : i6, eps12);
+      }
     }
+#pragma unroll
+    for (int j = 0; j < 2; ++j) accP[j] = accN[j];
+    cfxP = cfxN;
   }
-  if (!A.want_mom) return;
-  // the four lanes of a node (g = 0..3) hold partial sums over their rows
-#define EVLB2D_REDUCE(v) v += __shfl_xor(v, 16); v += __shfl_xor(v, 32)
-  EVLB2D_REDUCE(m.n); EVLB2D_REDUCE(m.jx); EVLB2D_REDUCE(m.jy); EVLB2D_REDUCE(m.pxx);
-  EVLB2D_REDUCE(m.pxy); EVLB2D_REDUCE(m.pyy); EVLB2D_REDUCE(m.rx); EVLB2D_REDUCE(m.ry);
-  EVLB2D_REDUCE(m.g0); EVLB2D_REDUCE(m.hx); EVLB2D_REDUCE(m.hy);
-#undef EVLB2D_REDUCE
-  if (valid && g == 0) finish_moments(m, A.mom, N, node, D.status, D.T_iso);
+  // velocity sums of the last row
+  __syncthreads();
+  if (A.want_mom && w == 0 && L0 < nsum * SW) fused_raw_sum(D, A, S, d, L0, x0, yb - 1);
 }
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
-  size_t tab_d, tab_i, f1, f2, mom, fld, status, total;
+  size_t tab_d, tab_i, f1, f2, mom, raw, fld, status, total;
   int navg, npair, halo;
 };
 
@@ -776,6 +946,7 @@ Layout make_layout(const evlb_params* p, const evlb::DiscTables& t) {
   L.f1 = off; off += fbytes;
   L.f2 = off; off += fbytes;
   L.mom = off; off += align256(sizeof(double) * 6 * (size_t)N);
+  L.raw = off; off += align256(sizeof(double) * NRAW * (size_t)N);
   L.fld = off; off += align256(sizeof(double) * NF * (size_t)N);
   L.status = off; off += 256;
   L.total = off;
@@ -809,7 +980,7 @@ int validate(const evlb_params* p) {
   if (p->n_sys != 1 || !p->nx) return EVLB_EINVAL;
   if (p->nx[0] < 8 || p->ny < 8) return EVLB_EINVAL;
   const long long N = (long long)p->nx[0] * p->ny;
-  if (N > (1ll << 22)) return EVLB_EINVAL;  // 32-bit buffer offsets of the velocity kernel
+  if (N > (1ll << 20)) return EVLB_EINVAL;  // 32-bit byte offsets within one distribution's 256 planes
   if (p->q != Q) return EVLB_EUNSUPPORTED;
   if (!(p->dx > 0) || !(p->dt > 0) || !std::isfinite(p->dx) || !std::isfinite(p->dt)) return EVLB_EINVAL;
   if (!(p->sigma > 0) || !std::isfinite(p->sigma) || !(p->phi_sigma >= 0) || !std::isfinite(p->phi_sigma))
@@ -930,58 +1101,68 @@ namespace {
 
 int launched() { return hipGetLastError() == hipSuccess ? EVLB_OK : EVLB_EHIP; }
 
-int launch_moments(Ctx* c, const double* f, double* out6, hipStream_t st, int stage_input = 1) {
-  const unsigned nb = (unsigned)((c->N + 255) / 256);
-  hipLaunchKernelGGL(moments_kernel, dim3(nb), dim3(256), 0, st, c->dev, f, out6, c->vel, stage_input);
+int launch_raw(Ctx* c, const double* f, hipStream_t st) {
+  const unsigned nb = (unsigned)((c->N + 3) / 4);  // one wavefront per node
+  hipLaunchKernelGGL(raw_sums_kernel, dim3(nb), dim3(256), 0, st, c->dev, f, (double*)(c->ws + c->L.raw), c->vel);
   return launched();
 }
 
 int launch_fields(Ctx* c, hipStream_t st) {
   const dim3 grid((c->nx + FTX - 1) / FTX, (c->ny + FTY - 1) / FTY);
   hipLaunchKernelGGL(fields_kernel, grid, dim3(FNT), fields_lds_bytes(c->L.halo), st, c->dev,
-                     (const double*)(c->ws + c->L.mom), (double*)(c->ws + c->L.fld), c->avg_ofs, c->avg_w,
+                     (const double*)(c->ws + c->L.raw), (double*)(c->ws + c->L.fld), c->avg_ofs, c->avg_w,
                      c->pair_ofs, c->pair_cx, c->pair_cy);
   return launched();
 }
 
-int launch_adv(Ctx* c, const AdvArgs& A, hipStream_t st) {
-  if (!(c->dev.term_mask & EVLB_TERM_ADV)) {
-    const long long nb = (2 * V * c->N + 255) / 256;
-    hipLaunchKernelGGL(combine_kernel, dim3((unsigned)nb), dim3(256), 0, st, c->dev, A);
-    return launched();
-  }
-  const long long strips = (long long)((c->nx + AW - 1) / AW) * ((c->ny + AR - 1) / AR) * 2 * V;
-  const long long nb = (strips + 3) / 4;
-  hipLaunchKernelGGL(adv_kernel, dim3((unsigned)nb), dim3(ANT), 0, st, c->dev, A, c->vel);
-  return launched();
+// Strips of SW columns, two distributions, and enough segments of rows for
+// about one workgroup per CU (at least 16 rows each: a segment re-reads the
+// six rows of its ring prologue).
+void fused_shape(const Ctx* c, int* nstrip, int* nseg, int* seglen) {
+  *nstrip = (c->nx + SW - 1) / SW;
+  int s = (256 + 2 * *nstrip - 1) / (2 * *nstrip);
+  const int smax = c->ny / 16 > 1 ? c->ny / 16 : 1;
+  if (s > smax) s = smax;
+  if (s < 1) s = 1;
+  *seglen = (c->ny + s - 1) / s;
+  *nseg = (c->ny + *seglen - 1) / *seglen;  // every segment non-empty
 }
 
-int launch_vel(Ctx* c, const VelArgs& A, hipStream_t st) {
-  const unsigned nb = (unsigned)(((c->nx + 63) / 64) * c->ny);
-  if (c->dev.term_mask & EVLB_TERM_FORCE)
-    hipLaunchKernelGGL(vel_kernel<true>, dim3(nb), dim3(256), 0, st, c->dev, A, c->vel, c->meq, c->dpm);
+template <bool ADV, bool FRC>
+void launch_fused(Ctx* c, const FusedArgs& A, dim3 grid, int first, hipStream_t st) {
+  if (first)
+    hipLaunchKernelGGL((fused_kernel<ADV, FRC, true>), grid, dim3(SNT), 0, st, c->dev, A, c->vel, c->meq, c->dpm);
   else
-    hipLaunchKernelGGL(vel_kernel<false>, dim3(nb), dim3(256), 0, st, c->dev, A, c->vel, c->meq, c->dpm);
-  return launched();
+    hipLaunchKernelGGL((fused_kernel<ADV, FRC, false>), grid, dim3(SNT), 0, st, c->dev, A, c->vel, c->meq, c->dpm);
 }
 
-// one evaluation: fields of the moments in the workspace, then
-// W = a f0 + b fs + c Adv(fs) and out = W + c R(fs)
-int stage(Ctx* c, const double* fs, const double* f0, double* W, double a, double b, double cc, int first,
+// one evaluation: the fields of the raw sums in the workspace, then
+// out = a f0 + b fs + c L(fs) and (want_mom) the raw sums of out
+int stage(Ctx* c, const double* fs, const double* f0, double* out, double a, double b, double cc, int first,
           int want_mom, hipStream_t st) {
   int rc = launch_fields(c, st);
   if (rc) return rc;
-  AdvArgs A{fs, f0, W, a, b, cc, first};
-  rc = launch_adv(c, A, st);
-  if (rc) return rc;
-  VelArgs B{fs, W, (const double*)(c->ws + c->L.fld), (double*)(c->ws + c->L.mom), cc, want_mom};
-  return launch_vel(c, B, st);
+  int nstrip, nseg, seglen;
+  fused_shape(c, &nstrip, &nseg, &seglen);
+  FusedArgs A{fs, f0, out, (const double*)(c->ws + c->L.fld), (double*)(c->ws + c->L.raw), a, b, cc, first,
+              want_mom, nstrip, seglen};
+  const dim3 grid((unsigned)(2 * nstrip * nseg));
+  const bool adv = (c->dev.term_mask & EVLB_TERM_ADV) != 0, frc = (c->dev.term_mask & EVLB_TERM_FORCE) != 0;
+  if (adv && frc)
+    launch_fused<true, true>(c, A, grid, first, st);
+  else if (adv)
+    launch_fused<true, false>(c, A, grid, first, st);
+  else if (frc)
+    launch_fused<false, true>(c, A, grid, first, st);
+  else
+    launch_fused<false, false>(c, A, grid, first, st);
+  return launched();
 }
 
 }  // namespace
 
 int set_equilibrium(Ctx* c, const double* n, const double* u, const double* T, double* f, hipStream_t st) {
-  const unsigned nb = (unsigned)((c->N + 255) / 256);
+  const unsigned nb = (unsigned)((c->N + 3) / 4);  // one wavefront per node
   hipLaunchKernelGGL(equilibrium_kernel, dim3(nb), dim3(256), 0, st, c->dev, n, u, T, f, c->meq);
   return launched();
 }
@@ -991,7 +1172,7 @@ int step(Ctx* c, double* f, int nsteps, hipStream_t st) {
   static const double RKB[3] = {1.0, 0.25, 2.0 / 3.0};
   double* f1 = (double*)(c->ws + c->L.f1);
   double* f2 = (double*)(c->ws + c->L.f2);
-  int rc = launch_moments(c, f, (double*)(c->ws + c->L.mom), st);
+  int rc = launch_raw(c, f, st);
   if (rc) return rc;
   const double dt = c->p.dt;
   for (int n = 0; n < nsteps; ++n) {
@@ -1006,21 +1187,22 @@ int step(Ctx* c, double* f, int nsteps, hipStream_t st) {
 }
 
 int rhs(Ctx* c, const double* f, double* L, hipStream_t st) {
-  int rc = launch_moments(c, f, (double*)(c->ws + c->L.mom), st);
+  int rc = launch_raw(c, f, st);
   if (rc) return rc;
   return stage(c, f, f, L, 0.0, 0.0, 1.0, 1, 0, st);
 }
 
 int moments(Ctx* c, const double* f, double* n, double* u, double* T, double* q, hipStream_t st) {
   double* m = (double*)(c->ws + c->L.mom);
-  int rc = launch_moments(c, f, m, st, 0);
-  if (rc) return rc;
-  const size_t nb = sizeof(double) * (size_t)c->N;
-  if (hipMemcpyAsync(n, m, nb, hipMemcpyDeviceToDevice, st) != hipSuccess ||
-      hipMemcpyAsync(u, m + c->N, 2 * nb, hipMemcpyDeviceToDevice, st) != hipSuccess ||
-      hipMemcpyAsync(T, m + 3 * c->N, nb, hipMemcpyDeviceToDevice, st) != hipSuccess)
+  const unsigned nb = (unsigned)((c->N + 3) / 4);  // one wavefront per node
+  hipLaunchKernelGGL(moments_kernel, dim3(nb), dim3(256), 0, st, c->dev, f, m, c->vel);
+  if (launched()) return EVLB_EHIP;
+  const size_t bytes = sizeof(double) * (size_t)c->N;
+  if (hipMemcpyAsync(n, m, bytes, hipMemcpyDeviceToDevice, st) != hipSuccess ||
+      hipMemcpyAsync(u, m + c->N, 2 * bytes, hipMemcpyDeviceToDevice, st) != hipSuccess ||
+      hipMemcpyAsync(T, m + 3 * c->N, bytes, hipMemcpyDeviceToDevice, st) != hipSuccess)
     return EVLB_EHIP;
-  if (q && hipMemcpyAsync(q, m + 4 * c->N, 2 * nb, hipMemcpyDeviceToDevice, st) != hipSuccess) return EVLB_EHIP;
+  if (q && hipMemcpyAsync(q, m + 4 * c->N, 2 * bytes, hipMemcpyDeviceToDevice, st) != hipSuccess) return EVLB_EHIP;
   return EVLB_OK;
 }
 

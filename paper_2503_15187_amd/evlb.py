@@ -223,8 +223,10 @@ def evlb_destroy(ctx):
 
 class Solver:
     """A context plus its workspace on the current device.  With ny > 0 the
-    context is the 2D path: states are (2, q, q, ny, nx) and vector node
-    fields (u, q) carry an x and a y component."""
+    context is the 2D path: states are node-major (2, ny, nx, q, q) (the
+    q^2 velocities of a node contiguous, see evlb.h) and vector node fields
+    (u, q) carry an x and a y component; `planes` and `from_planes` convert
+    to and from the per-velocity-plane view (2, q, q, ny, nx)."""
 
     def __init__(self, q, dx, dt, nx, device=None, stream=None, **kw):
         self.params = make_params(q, dx, dt, nx, **kw)
@@ -251,8 +253,19 @@ class Solver:
 
     def new_state(self):
         if self.dim == 2:
-            return torch.empty((2, self.q, self.q) + self.shape2d, dtype=torch.float64, device=self.device)
+            return torch.empty((2,) + self.shape2d + (self.q, self.q), dtype=torch.float64, device=self.device)
         return torch.empty((2, self.q, self.n_tot), dtype=torch.float64, device=self.device)
+
+    @staticmethod
+    def planes(f):
+        """A 2D state (or right-hand side) (2, ny, nx, q, q) as the view
+        (2, q, q, ny, nx): [d][k][l] is the plane of velocity (p_k, p_l)."""
+        return f.permute(0, 3, 4, 1, 2)
+
+    @staticmethod
+    def from_planes(x):
+        """The node-major 2D state (2, ny, nx, q, q) of planes (2, q, q, ny, nx)."""
+        return x.permute(0, 3, 4, 1, 2).contiguous()
 
     def equilibrium(self, n, u, T, stream=None):
         f = self.new_state()

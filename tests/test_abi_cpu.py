@@ -146,8 +146,9 @@ def test_validate_rejects_2d(kw, code):
 def test_workspace_2d_scales_with_nodes():
     a = P.evlb_workspace_bytes(_p2(nx=256, ny=256))
     b = P.evlb_workspace_bytes(_p2(nx=256, ny=512))
-    # two stage buffers [2][256][n], moments [6][n] and node fields [18][n]
-    per_node = 2 * 2 * 256 * 8 + 6 * 8 + 18 * 8
+    # two stage buffers [2][256][n], moments [6][n], raw velocity sums
+    # [11][n] and node fields [18][n]
+    per_node = 2 * 2 * 256 * 8 + 6 * 8 + 11 * 8 + 18 * 8
     assert abs((b - a) - 256 * 256 * per_node) < 4096
 
 

@@ -41,6 +41,16 @@ def td(a):
     return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=DEV)
 
 
+def tstate(F, G):
+    """The node-major device state of the oracle's planes F, G (q, q, ny, nx)."""
+    return E.Solver.from_planes(td(np.stack([F, G])))
+
+
+def planes(f):
+    """A device state or right-hand side as host planes (2, q, q, ny, nx)."""
+    return E.Solver.planes(f).cpu().numpy()
+
+
 
 
 def tables(c, **kw):
@@ -109,10 +119,10 @@ def test_equilibrium_and_moments_2d():
     tb = tables(c)
     F, G = step2d.initial_state(n, ux, uy, T, tb)
     s = solver(c, 40, 24)
-    f = s.equilibrium(td(n), td(np.stack([ux, uy])), td(T)).cpu().numpy()
+    f = planes(s.equilibrium(td(n), td(np.stack([ux, uy])), td(T)))
     check(f, [F, G], 1e-13)
     Fp, Gp = oracle_state(c, n, ux, uy, T, tb)
-    mom = s.moments(td(np.stack([Fp, Gp]))).cpu().numpy()
+    mom = s.moments(tstate(Fp, Gp)).cpu().numpy()
     ref = step2d.moments(Fp, Gp, tb)
     for i in range(6):
         assert np.max(np.abs(mom[i] - ref[i].ravel())) <= 1e-13 * np.max(np.abs(ref[i])) + 1e-16, i
@@ -130,7 +140,7 @@ def test_rhs_terms_2d(mask, nx, ny):
     F, G = oracle_state(c, n, ux, uy, T, tb)
     LF, LG = step2d.rhs(F, G, tb)
     s = solver(c, nx, ny, **kw)
-    L = s.rhs(td(np.stack([F, G]))).cpu().numpy()
+    L = planes(s.rhs(tstate(F, G)))
     check(L, [LF, LG], 1e-11)
 
 
@@ -140,7 +150,7 @@ def test_rhs_force_model_none_2d():
     tb = tables(c, **kw)
     F, G = oracle_state(c, n, ux, uy, T, tb)
     LF, LG = step2d.rhs(F, G, tb)
-    L = solver(c, 40, 16, force_model=2, g_ext=0.02).rhs(td(np.stack([F, G]))).cpu().numpy()
+    L = planes(solver(c, 40, 16, force_model=2, g_ext=0.02).rhs(tstate(F, G)))
     check(L, [LF, LG], 1e-11)
 
 
@@ -155,10 +165,10 @@ def test_100_steps_2d_small_periodic_grid():
     F, G = oracle_state(c, n, ux, uy, T, tb)
     Fo, Go = step2d.run(F, G, tb, nsteps)
     s = solver(c, nx, ny)
-    f = td(np.stack([F, G]))
+    f = tstate(F, G)
     s.step(f, nsteps)
     assert s.status() == E.EVLB_OK
-    err, rerr = check(f.cpu().numpy(), [Fo, Go], 1e-11, steps=nsteps)
+    err, rerr = check(planes(f), [Fo, Go], 1e-11, steps=nsteps)
     print(f"2D 100-step rel err {err:.3e}, per row {rerr:.3e}", flush=True)
 
 
@@ -171,10 +181,10 @@ def test_steps_2d(nsteps):
     F, G = oracle_state(c, n, ux, uy, T, tb)
     Fo, Go = step2d.run(F, G, tb, nsteps)
     s = solver(c, nx, ny)
-    f = td(np.stack([F, G]))
+    f = tstate(F, G)
     s.step(f, nsteps)
     assert s.status() == E.EVLB_OK
-    check(f.cpu().numpy(), [Fo, Go], 1e-11, steps=nsteps)
+    check(planes(f), [Fo, Go], 1e-11, steps=nsteps)
 
 
 def test_uniform_state_stationary_2d():
@@ -192,23 +202,24 @@ def test_conservation_2d():
     tb = tables(c)
     F, G = oracle_state(c, n, ux, uy, T, tb)
     s = solver(c, 64, 48)
-    f = td(np.stack([F, G]))
+    f = tstate(F, G)
+    fp = E.Solver.planes(f)  # a view: follows the steps
     v = torch.tensor(tb.v, dtype=torch.float64, device=DEV)
-    mass0 = f[0].sum().item()
-    px0 = (v[:, None, None, None] * f[0]).sum().item()
-    py0 = (v[None, :, None, None] * f[0]).sum().item()
-    scale = (v.abs()[:, None, None, None] * f[0]).sum().item()
+    mass0 = fp[0].sum().item()
+    px0 = (v[:, None, None, None] * fp[0]).sum().item()
+    py0 = (v[None, :, None, None] * fp[0]).sum().item()
+    scale = (v.abs()[:, None, None, None] * fp[0]).sum().item()
     s.step(f, 10)
-    assert abs(f[0].sum().item() - mass0) < 1e-13 * mass0
-    assert abs((v[:, None, None, None] * f[0]).sum().item() - px0) < 1e-13 * scale
-    assert abs((v[None, :, None, None] * f[0]).sum().item() - py0) < 1e-13 * scale
+    assert abs(fp[0].sum().item() - mass0) < 1e-13 * mass0
+    assert abs((v[:, None, None, None] * fp[0]).sum().item() - px0) < 1e-13 * scale
+    assert abs((v[None, :, None, None] * fp[0]).sum().item() - py0) < 1e-13 * scale
 
 
 def test_nonfinite_status_2d():
     c, n, ux, uy, T = small_case(32, 16)
     s = solver(c, 32, 16)
     f = s.equilibrium(td(n), td(np.stack([ux, uy])), td(T))
-    f[0, :, :, 3, 5] = -1.0
+    f[0, 3, 5] = -1.0  # every velocity of F at node (y, x) = (3, 5)
     s.step(f, 1)
     assert s.status() == E.EVLB_ENONFINITE
     assert s.status() == E.EVLB_OK  # cleared
@@ -228,7 +239,7 @@ def full_state():
     c, n, ux, uy, T = workloads.phase_separation_2d()
     s = solver(c, c["nx"], c["ny"])
     f = s.equilibrium(td(n), td(np.stack([ux, uy])), td(T))
-    f.mul_(perturbation_torch(c["ny"], c["nx"]))
+    f.mul_(E.Solver.from_planes(perturbation_torch(c["ny"], c["nx"])))
     return c, n, ux, uy, T, s, f
 
 
@@ -253,7 +264,7 @@ def test_full_size_rhs_sampled(full_state):
         cy = slice(m, m + b)
         ys = torch.tensor((yc + np.arange(b)) % c["ny"], device=DEV)
         xs = torch.tensor((xc + np.arange(b)) % c["nx"], device=DEV)
-        got = L.index_select(3, ys).index_select(4, xs).cpu().numpy()
+        got = E.Solver.planes(L).index_select(3, ys).index_select(4, xs).cpu().numpy()
         check(got, [LF[:, :, cy, cy], LG[:, :, cy, cy]], 1e-11, what=repr((yc, xc)))
 
 
@@ -276,5 +287,5 @@ def test_full_size_step_sampled(full_state):
                                   _window(uy, y0, x0, h, w), _window(T, y0, x0, h, w), tb)
     P = perturbation_at(yi, xi)
     Fo, Go = step2d.rk3_step(Fw * P[0], Gw * P[1], tb)
-    got = g[:, :, :, yc:yc + b, xc:xc + b].cpu().numpy()
+    got = E.Solver.planes(g)[:, :, :, yc:yc + b, xc:xc + b].cpu().numpy()
     check(got, [Fo[:, :, m:m + b, m:m + b], Go[:, :, m:m + b, m:m + b]], 1e-11)

@@ -86,12 +86,12 @@ def test_isothermal_2d_rhs_and_step():
     F, G = step2d.initial_state(n, ux, uy, T, tb)
     LF, LG = step2d.rhs(F, G, tb)
     s = E.Solver(16, c["dx"], c["dt"], 40, ny=24, T_iso=T_iso)
-    L = s.rhs(td(np.stack([F, G]))).cpu().numpy()
+    L = E.Solver.planes(s.rhs(E.Solver.from_planes(td(np.stack([F, G]))))).cpu().numpy()
     check(L, [LF, LG], 1e-11)
     Fo, Go = step2d.rk3_step(F, G, tb)
-    f = td(np.stack([F, G]))
+    f = E.Solver.from_planes(td(np.stack([F, G])))
     s.step(f, 1)
-    check(f.cpu().numpy(), [Fo, Go], 1e-11)
+    check(E.Solver.planes(f).cpu().numpy(), [Fo, Go], 1e-11)
 
 
 TEMPS = (0.55, 0.6, 0.65, 0.7, 0.74)
