@@ -364,7 +364,8 @@ __global__ __launch_bounds__(FNT) void fields_kernel(Dev D, const double* __rest
 //  post(y)  the work that reads other wavefronts' rows or writes what they
 //           read: f^(s) of row y - 1 from acc(y - 1), the (Dp x I) f term and
 //           the strip-edge face of row y - 1, its store and its per-wavefront
-//           velocity sums (each lane one weighted term of the raw sums);
+//           terms of the raw velocity sums (a weight matrix times the row's
+//           16 x 8 values on the MFMA);
 //           wavefront 0 the raw velocity sums of row y - 2, 1 the Hermite
 //           coefficients a_m(u, T) of row y + 3, 2 the expansions e_k(u_x),
 //           e_l(u_y) of row y + 2 (one MFMA chain over 8 nodes x 2 axes), 3
@@ -425,30 +426,33 @@ struct FusedSmem {
 static_assert(sizeof(FusedSmem) <= 160 * 1024, "fused stage LDS exceeds 160 KiB");
 
 // WENO-5 (Jiang & Shu) value at a face from the five values v0 .. v4 ordered
-// from the upwind side (v2 is the node upwind of the face): candidates 6 q_r,
-// smoothness 12 beta_r = 13 a^2 + 3 b^2, weights d_r / (eps + beta_r)^2 over
-// their common denominator with 10 d = (1, 6, 3) (every factor cancels), the
-// division through a hardware reciprocal refined by two Newton steps.
+// from the upwind side (v2 is the node upwind of the face).  Candidates
+// c_r, smoothness 12 beta_r = 13 a_r^2 + 3 b_r^2, weights d_r / (eps +
+// beta_r)^2 normalised: with t_r = (12 eps + 12 beta_r)^2 and 10 d = (1, 6, 3)
+// the value is (t1 t2 c0 + 6 t0 t2 c1 + 3 t0 t1 c2) / (t1 t2 + 6 t0 t2 +
+// 3 t0 t1) (every common factor cancels); 6 c1 and 3 c2 are formed directly.
+// The division goes through a hardware reciprocal refined by two Newton
+// steps.
 __device__ __forceinline__ double weno5(double v0, double v1, double v2, double v3, double v4, double eps12) {
-  const double q0 = fma(2.0, v0, fma(-7.0, v1, 11.0 * v2));
-  const double q1 = fma(5.0, v2, fma(2.0, v3, -v1));
-  const double q2 = fma(2.0, v2, fma(5.0, v3, -v4));
-  const double a0 = fma(-2.0, v1, v0 + v2), c0 = fma(-4.0, v1, fma(3.0, v2, v0));
-  const double a1 = fma(-2.0, v2, v1 + v3), c1 = v1 - v3;
-  const double a2 = fma(-2.0, v3, v2 + v4), c2 = fma(-4.0, v3, fma(3.0, v2, v4));
-  double t0 = eps12 + fma(13.0 * a0, a0, 3.0 * (c0 * c0));
-  double t1 = eps12 + fma(13.0 * a1, a1, 3.0 * (c1 * c1));
-  double t2 = eps12 + fma(13.0 * a2, a2, 3.0 * (c2 * c2));
+  const double c0 = fma(1.0 / 3.0, v0, fma(-7.0 / 6.0, v1, (11.0 / 6.0) * v2));
+  const double c1x6 = fma(5.0, v2, fma(2.0, v3, -v1));
+  const double c2x3 = fma(2.5, v3, fma(-0.5, v4, v2));
+  const double a0 = fma(-2.0, v1, v0 + v2), b0 = fma(-4.0, v1, fma(3.0, v2, v0));
+  const double a1 = fma(-2.0, v2, v1 + v3), b1 = v1 - v3;
+  const double a2 = fma(-2.0, v3, v2 + v4), b2 = fma(-4.0, v3, fma(3.0, v2, v4));
+  double t0 = fma(13.0 * a0, a0, fma(3.0 * b0, b0, eps12));
+  double t1 = fma(13.0 * a1, a1, fma(3.0 * b1, b1, eps12));
+  double t2 = fma(13.0 * a2, a2, fma(3.0 * b2, b2, eps12));
   t0 *= t0;
   t1 *= t1;
   t2 *= t2;
-  const double w0 = t1 * t2, w1 = 6.0 * (t0 * t2), w2 = 3.0 * (t0 * t1);
-  const double num = fma(w2, q2, fma(w1, q1, w0 * q0));
-  const double den = w0 + w1 + w2;
+  const double u0 = t1 * t2, u1 = t0 * t2, u2 = t0 * t1;
+  const double num = fma(u2, c2x3, fma(u1, c1x6, u0 * c0));
+  const double den = fma(3.0, u2, fma(6.0, u1, u0));
   double r = __builtin_amdgcn_rcp(den);
   r = fma(r, fma(-den, r, 1.0), r);
   r = fma(r, fma(-den, r, 1.0), r);
-  return (num * r) * (1.0 / 6.0);
+  return num * r;
 }
 
 // Lane i of every 16-lane row takes lane i + 1's value (lane 15: 0).
@@ -459,35 +463,18 @@ __device__ __forceinline__ double row_next(double v) {
   return __builtin_bit_cast(double, (unsigned long long)(unsigned)lo | ((unsigned long long)(unsigned)hi << 32));
 }
 
-// Sum over the eight lanes of one column (lanes c + 8 r, r < 8), every lane
-// gets it: over the lanes i, i + 16, i + 32, i + 48 by the gfx950 cross-row
-// swaps of 16-lane rows and 32-lane halves, then over i and i ^ 8 by a DPP
-// rotation of each 16-lane row by 8.
-__device__ __forceinline__ double col8_sum(double v) {
-  const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
-  const unsigned lo = (unsigned)b, hi = (unsigned)(b >> 32);
-  const auto l16 = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
-  const auto h16 = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
-  const double s = __builtin_bit_cast(double, (unsigned long long)l16[0] | ((unsigned long long)h16[0] << 32)) +
-                   __builtin_bit_cast(double, (unsigned long long)l16[1] | ((unsigned long long)h16[1] << 32));
-  const unsigned long long sb = __builtin_bit_cast(unsigned long long, s);
-  const unsigned slo = (unsigned)sb, shi = (unsigned)(sb >> 32);
-  const auto l32 = __builtin_amdgcn_permlane32_swap(slo, slo, false, false);
-  const auto h32 = __builtin_amdgcn_permlane32_swap(shi, shi, false, false);
-  const double t = __builtin_bit_cast(double, (unsigned long long)l32[0] | ((unsigned long long)h32[0] << 32)) +
-                   __builtin_bit_cast(double, (unsigned long long)l32[1] | ((unsigned long long)h32[1] << 32));
-  const unsigned long long tb = __builtin_bit_cast(unsigned long long, t);
-  const int rlo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)tb, 0x128, 0xf, 0xf, false);  // row_ror:8
-  const int rhi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(tb >> 32), 0x128, 0xf, 0xf, false);
-  return t + __builtin_bit_cast(double, (unsigned long long)(unsigned)rlo | ((unsigned long long)(unsigned)rhi << 32));
-}
-
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 
 constexpr int BUF_DWORD3 = 0x00020000;
 
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t buf(const double* base) {
   return __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, -1, BUF_DWORD3);
+}
+// A buffer of 2^31 bytes: an access at BUF_DROP (no scalar offset) is out of
+// range, so a store there is dropped and a load returns 0.
+constexpr unsigned BUF_DROP = 0xfffffff0u;
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf2g(const double* base) {
+  return __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, (int)0x80000000u, BUF_DWORD3);
 }
 __device__ __forceinline__ double bload(__amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so) {
   return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, vo, so, 0));
@@ -564,24 +551,6 @@ __device__ __forceinline__ void fused_expansions(FusedSmem& S, int fb, int L) {
   for (int j = 0; j < 4; ++j) S.EK[fb][col16 >> 3][4 * j + c4][col16 & 7] = e[j];
 }
 
-// The term of raw velocity sum s contributed by one k from the sums
-// M_i = sum_l p_l^i f over the wavefront's l (p = p_k):
-//   F: n: M0, j_x: p M0, j_y: M1, P_xx: p^2 M0, P_xy: p M1, P_yy: M2,
-//      r_x: p^3 M0 + p M2, r_y: p^2 M1 + M3;
-//   G: g0: M0, h_x: p M0, h_y: M1.
-// Term s is p^a1 M_i1 (+ p^(a1 - 2) M_(i1 + 2) for r_x, r_y); i1 and a1 are
-// read from 2-bit fields of constants, so that lanes with different s run
-// the same instructions.
-__device__ __forceinline__ double fused_sum_term(int d, int s, const double* m, double p) {
-  const int i1 = ((d == 0 ? 18704 : 16) >> (2 * s)) & 3;
-  const int a1 = ((d == 0 ? 45444 : 4) >> (2 * s)) & 3;
-  const double p2 = p * p;
-  const double w1 = ((a1 & 1) ? p : 1.0) * ((a1 & 2) ? p2 : 1.0);
-  const double mi = i1 == 0 ? m[0] : (i1 == 1 ? m[1] : (i1 == 2 ? m[2] : m[3]));
-  const double m2 = d == 0 && s >= 6 ? (s == 6 ? m[2] : m[3]) : 0.0;
-  return fma(s == 6 ? p : 1.0, m2, w1 * mi);
-}
-
 // Raw velocity sum s = t / SW of row y at column t % SW: the sum over the 16
 // wavefronts' terms.
 __device__ __forceinline__ void fused_raw_sum(const Dev& D, const FusedArgs& A, const FusedSmem& S, int d, int t,
@@ -626,7 +595,7 @@ __global__ __launch_bounds__(SNT) void fused_kernel(Dev D, FusedArgs A, const do
 
   const long long dofs = (long long)d * V * D.ntot;
   const __amdgpu_buffer_rsrc_t rs = buf(A.fs + dofs), r0 = buf((FIRST ? A.fs : A.f0) + dofs);
-  const __amdgpu_buffer_rsrc_t ro = buf(A.out + dofs), rf = buf(A.fld);
+  const __amdgpu_buffer_rsrc_t ro = buf2g(A.out + dofs), rf = buf(A.fld);
   auto wrapx = [&](int x) { x %= nx; return x < 0 ? x + nx : x; };
   // per-lane byte offset of velocity (w, r) at the lane's column; (w, r + 8)
   // is 64 bytes further, a row nx V doubles further
@@ -649,6 +618,26 @@ __global__ __launch_bounds__(SNT) void fused_kernel(Dev D, FusedArgs A, const do
   const unsigned rowf = (unsigned)nx * 8u;
   const double pk = velg[w];
   const double pxi = pk * D.inv_dx;
+  // MFMA A operand of the raw-sum weights of this wavefront's k: lane i + 16 c
+  // holds C[i][c + 4 b] for sum i (p = p_k, q = p_l):
+  //   F: n: 1, j_x: p, j_y: q, P_xx: p^2, P_xy: p q, P_yy: q^2,
+  //      r_x: p (p^2 + q^2), r_y: q (p^2 + q^2);  G: g0: 1, h_x: p, h_y: q
+  double mop[4];
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    const int i = L0 & 15;
+    const double q = velg[(L0 >> 4) + 4 * b], pq2 = pk * pk + q * q;
+    double cw = 0.0;
+    if (i == 0) cw = 1.0;
+    else if (i == 1) cw = pk;
+    else if (i == 2) cw = q;
+    else if (d == 0 && i == 3) cw = pk * pk;
+    else if (d == 0 && i == 4) cw = pk * q;
+    else if (d == 0 && i == 5) cw = q * q;
+    else if (d == 0 && i == 6) cw = pk * pq2;
+    else if (d == 0 && i == 7) cw = q * pq2;
+    mop[b] = cw;
+  }
   const bool PX = pk > 0.0;  // uniform per wavefront
   const double bb = FIRST ? A.a + A.b : A.b;  // the first stage has f^n = f^(s-1)
 
@@ -715,6 +704,9 @@ __global__ __launch_bounds__(SNT) void fused_kernel(Dev D, FusedArgs A, const do
     const int yp = y & 1;
     double accN[2] = {0.0, 0.0}, cfxN = 0.0;
     // ---------------- pre(y) ----------------
+    double* Tw = &S.T[16 * w * TS];  // this wavefront's 16 velocities
+    const double* cf = &S.CF[y & 3][0][col];
+    double part[2] = {0.0, 0.0}, base[2] = {0.0, 0.0};
     if (y < yb) {
       if (y > ya) {
         // advance the ring: the row loaded into R0 last row moves to the end
@@ -728,11 +720,9 @@ __global__ __launch_bounds__(SNT) void fused_kernel(Dev D, FusedArgs A, const do
           R5[j][4] = t;
         }
       }
-      double* Tw = &S.T[16 * w * TS];  // this wavefront's 16 velocities
       double* fi = &S.FI[yp][w][0];
-      const double* cf = &S.CF[y & 3][0][col];
       const double nu = cf[CF_NU * SW];
-      double cur[2], part[2], base[2];
+      double cur[2];
       cur[0] = R5[0][1];  // row y
       cur[1] = R5[1][2];
 #pragma unroll
@@ -759,24 +749,27 @@ __global__ __launch_bounds__(SNT) void fused_kernel(Dev D, FusedArgs A, const do
         fyl[0] = fyr0;
         fyl[1] = fyr1;
       }
-      // in flight across the rest of this iteration: node fields of row
-      // y + 4 (issued first: the wait for it in the next iteration then
-      // leaves the later loads in flight), the ring's next row (into the slot
-      // just dropped), f^n and the halo of row y + 1 (unconditional, past the
-      // segment too: a load under a condition would make the compiler copy
-      // the register at the loop latch, which waits for every load in flight)
-      fq = bload(rf, fvo, rowsf(y + 4));
+    }
+    // in flight across the rest of this iteration: node fields of row y + 4
+    // (issued first: the wait for it in the next iteration then leaves the
+    // later loads in flight), the ring's next row (into the slot just
+    // dropped), f^n and the halo of row y + 1.  Outside the condition, and
+    // past the segment too: a load under a condition would make the
+    // compiler copy the register at the loop latch, which waits for every
+    // load in flight.
+    fq = bload(rf, fvo, rowsf(y + 4));
 #pragma unroll
-      for (int j = 0; j < 2; ++j) R5[j][0] = bload(rs, vo, j * pso + rowso(y + 4 - j));  // row (y + 1) + 3 - j
-      {
-        const unsigned so1 = rowso(y + 1);
-        if (!FIRST) {
+    for (int j = 0; j < 2; ++j) R5[j][0] = bload(rs, vo, j * pso + rowso(y + 4 - j));  // row (y + 1) + 3 - j
+    {
+      const unsigned so1 = rowso(y + 1);
+      if (!FIRST) {
 #pragma unroll
-          for (int j = 0; j < 2; ++j) f0v[j] = bload(r0, vo, j * pso + so1);
-        }
-        hv[0] = bload(rs, hvoA, so1);
-        hv[1] = bload(rs, hvoB, so1);
+        for (int j = 0; j < 2; ++j) f0v[j] = bload(r0, vo, j * pso + so1);
       }
+      hv[0] = bload(rs, hvoA, so1);
+      hv[1] = bload(rs, hvoB, so1);
+    }
+    if (y < yb) {
       if (ADV) {
         // x faces from this wavefront's LDS row: each lane the face on its
         // left, the face on its right from the next lane (the last column:
@@ -830,39 +823,39 @@ __global__ __launch_bounds__(SNT) void fused_kernel(Dev D, FusedArgs A, const do
     }
     __syncthreads();
     // ---------------- post(y) ----------------
-    if (y > ya) {
-      // f^(s) of row y - 1
+    {
+      // f^(s) of row y - 1 (y > ya).  The stores run every iteration, those
+      // with nothing to store at an offset past the buffer, so that every
+      // iteration issues the same vector memory operations and the wait for
+      // a load issued before them never has to drain them.
       const int pb = (y - 1) & 1;
-      const unsigned so = rowso(y - 1);
-      double sm[4] = {0, 0, 0, 0};
+      const bool live = y > ya;
+      const unsigned so = live && x0 + col < nx ? vo + rowso(y - 1) : BUF_DROP;
+      double* Tw = &S.T[16 * w * TS];
 #pragma unroll
       for (int j = 0; j < 2; ++j) {
         const int l = r + 8 * j;
-        const double plb = S.vel[l];
         double o = accP[j];
-        if (FRC) o = fma(-cfxP, S.DX[pb][w][8 * (l ^ (2 * (w & 1))) + col], o);
-        if (ADV && col == SW - 1) o = fma(-A.c * pxi, S.T[(16 * w + l) * TS + 22 + pb], o);
-        if (x0 + col < nx) bstore(o, ro, vo, j * pso + so);
-        if (A.want_mom) {
-          // sums over l of p_l^i f^(s) for this wavefront's k (F: i < 4, G: i < 2)
-          const double a1 = plb * o;
-          sm[0] += o;
-          sm[1] += a1;
-          if (d == 0) {
-            const double a2 = plb * a1;
-            sm[2] += a2;
-            sm[3] += plb * a2;
-          }
+        if (live) {
+          if (FRC) o = fma(-cfxP, S.DX[pb][w][8 * (l ^ (2 * (w & 1))) + col], o);
+          if (ADV && col == SW - 1) o = fma(-A.c * pxi, S.T[(16 * w + l) * TS + 22 + pb], o);
         }
+        bstore(o, ro, so == BUF_DROP ? BUF_DROP : so + j * pso, 0);
+        Tw[l * TS + 14 + col] = o;  // free until pre(y + 1)
       }
-      if (A.want_mom) {
-        // every lane of the column gets M_0 .. M_3, lane r writes term r
-        double m[4] = {0.0, 0.0, 0.0, 0.0};
+      if (live && A.want_mom) {
+        // this wavefront's terms of the raw sums, C f^(s) with C[s][l] the
+        // weights of sum s (mop), on the MFMA: B[c][col16] = f^(s)(w, l =
+        // c + 4 b) at column col16 & 7, rows s = 4 j + c of the result
+        const int c4 = L >> 4, c8 = L & 7;
+        dbl4 dd = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int s = 0; s < 4; ++s)
-          if (s < (d == 0 ? 4 : 2)) m[s] = col8_sum(sm[s]);
-        const double t = fused_sum_term(d, r, m, pk);
-        if (r < nsum) S.mred[pb][w][r][col] = t;
+        for (int b = 0; b < 4; ++b)
+          dd = __builtin_amdgcn_mfma_f64_16x16x4f64(mop[b], Tw[(c4 + 4 * b) * TS + 14 + c8], dd, 0, 0, 0);
+        if ((L & 8) == 0) {
+          S.mred[pb][w][c4][c8] = dd[0];
+          S.mred[pb][w][4 + c4][c8] = dd[1];
+        }
       }
     }
     // the serial chains on the oldest wavefront of four SIMDs (the arbiter
