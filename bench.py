@@ -159,6 +159,90 @@ def measured_traffic(workload, kernel):
     return e["bytes_per_launch"]
 
 
+def _kernel_names(raw):
+    """The full name (template arguments without spaces) and the family
+    (no template arguments) of a kernel name as rocprofv3 prints it."""
+    n = raw.replace("(anonymous namespace)::", "")
+    if n.startswith("void "):
+        n = n[5:]
+    depth, cut = 0, len(n)
+    for i, ch in enumerate(n):  # the argument list: the first '(' outside <>
+        if ch == "<":
+            depth += 1
+        elif ch == ">":
+            depth -= 1
+        elif ch == "(" and depth == 0:
+            cut = i
+            break
+    n = n[:cut].replace(" ", "")
+    n = n.split("::")[-1] if "<" not in n else n[:n.index("<")].split("::")[-1] + n[n.index("<"):]
+    return n, n.split("<")[0]
+
+
+def write_traffic(workload, fetch_csv, write_csv, commands):
+    """Per-launch HBM bytes of every kernel of one workload's counter runs
+    (rocprofv3 --pmc FETCH_SIZE, resp. WRITE_SIZE, of bench.py with
+    --calibrate-copy, whose last device copy moves 256 MiB and calibrates
+    both counters) into profiles/hbm_traffic.txt, keyed workload/kernel for
+    the full name and for the family (the mean over its variants)."""
+    import csv
+    import hashlib
+    from collections import defaultdict
+
+    def per_kernel(path, counter):
+        rows = [r for r in csv.DictReader(open(path)) if r["Counter_Name"] == counter]
+        per = defaultdict(lambda: defaultdict(float))
+        order = []
+        for r in rows:
+            per[r["Kernel_Name"]][r["Dispatch_Id"]] += float(r["Counter_Value"])
+            order.append((int(r["Dispatch_Id"]), r["Kernel_Name"]))
+        copies = sorted(d for d, k in order if "copyBuffer" in k)
+        if not copies:
+            raise SystemExit(f"{path}: no device copy to calibrate against (run with --calibrate-copy)")
+        last = copies[-1]
+        cal = next(v[str(last)] for k, v in per.items() if str(last) in v)
+        return per, cal
+
+    fetch, fcal = per_kernel(fetch_csv, "FETCH_SIZE")
+    write, wcal = per_kernel(write_csv, "WRITE_SIZE")
+    sf, sw = 262144.0 / fcal, 262144.0 / wcal
+    acc = defaultdict(lambda: [0.0, 0.0, 0])
+    ns = "evlb2d::" if workload.endswith("_2d") else "evlb::"  # the library's kernels of this dimension
+    for raw, vals in fetch.items():
+        if ns not in raw:
+            continue
+        full, fam = _kernel_names(raw)
+        wv = write.get(raw, {})
+        for d, v in vals.items():
+            for key in {full, fam}:
+                a = acc[key]
+                a[0] += v * 1024.0 * sf
+                a[1] += wv.get(d, 0.0) * 1024.0 * sw
+                a[2] += 1
+    src = "paper_2503_15187_amd/csrc/" + ("evlb2d.hip" if workload.endswith("_2d") else "evlb.hip")
+    with open(os.path.join(ROOT, src), "rb") as fh:
+        sha = hashlib.sha256(fh.read()).hexdigest()
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.txt")
+    try:
+        rec = json.load(open(path))
+    except (OSError, ValueError):
+        rec = {"entries": {}, "commands": {}}
+    if not isinstance(rec.get("commands"), dict):
+        rec["commands"] = {}
+    rec["entries"] = {k: v for k, v in rec["entries"].items() if not k.startswith(workload + "/")}
+    for key, (fb, wb, n) in sorted(acc.items()):
+        rec["entries"][f"{workload}/{key}"] = {
+            "bytes_per_launch": (fb + wb) / n, "fetch_bytes": fb / n, "write_bytes": wb / n, "launches": n,
+            "source": src, "source_sha256": sha}
+    rec["calibration"] = {"copy_bytes": 256 * 1024 * 1024, "scale_fetch": sf, "scale_write": sw,
+                          "copy_fetch_kib": fcal, "copy_write_kib": wcal}
+    rec["commands"][workload] = commands
+    with open(path, "w") as fh:
+        json.dump(rec, fh, indent=1)
+    for key, (fb, wb, n) in sorted(acc.items()):
+        print(f"{workload}/{key}: {(fb + wb) / n:.4g} B per launch ({n} launches)")
+
+
 def copy_bandwidth(torch, dev, mib=1024, reps=10):
     """Context for the roofline: the rate of a plain device-to-device copy of
     `mib` MiB (read + write bytes over the copy time, HIP events on the
@@ -243,7 +327,7 @@ def measure(E, torch, dev, q, dx, dt, nx, n, u, T, steps, warmup, mode=None, til
     }
 
 
-KERNELS_2D = ("fields_kernel", "adv_kernel", "vel_kernel<true>")
+KERNELS_2D = ("fields_kernel", "fused_kernel")
 
 
 def measure_2d(E, torch, dev, steps, warmup):
@@ -420,9 +504,16 @@ def main():
                     help="launch per-stage kernels one by one instead of replaying a captured HIP graph")
     ap.add_argument("--no-autotune", action="store_true",
                     help="use the library's default launch shape (one kernel per stage) instead of timing candidates")
+    ap.add_argument("--traffic-from", nargs=3, metavar=("WORKLOAD", "FETCH_CSV", "WRITE_CSV"),
+                    help="write profiles/hbm_traffic.txt entries of WORKLOAD from rocprofv3 counter runs and exit "
+                         "(no device use); the commands that made them follow as --traffic-command")
+    ap.add_argument("--traffic-command", action="append", default=[])
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="after timing, run one 256 MiB device-to-device copy (a reference for HBM byte counters)")
     args = ap.parse_args()
+    if args.traffic_from:
+        write_traffic(*args.traffic_from, args.traffic_command)
+        return
     if args.gpus != 1:
         print("bench.py: the library runs on one GPU only; a multi-GPU (domain-decomposed) path is "
               "not implemented. Run with --gpus 1.", file=sys.stderr)
