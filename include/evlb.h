@@ -153,10 +153,29 @@ size_t evlb_workspace_bytes(const evlb_params* params);
 int evlb_init(const evlb_params* params, void* d_workspace, size_t ws_bytes,
               void* hip_stream, evlb_ctx** out);
 
+/* Largest workspace evlb_init_noalloc serves (64 MiB: every dim-1 case up to
+ * about 80 000 nodes, dim 2 up to about 90 x 90 nodes). */
+#define EVLB_NOALLOC_MAX_BYTES ((size_t)64 << 20)
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): evlb_init with
+ * the library's own workspace, a static device array of
+ * EVLB_NOALLOC_MAX_BYTES per device that the library holds until the
+ * process ends, instead of a caller buffer.  Calls no hipMalloc or other
+ * allocating routine.  Returns EVLB_EWORKSPACE if
+ * evlb_workspace_bytes(params) exceeds EVLB_NOALLOC_MAX_BYTES, EVLB_EHIP if
+ * the array's device address cannot be obtained.  Every context made this
+ * way on one device shares that device's array: a new one re-initialises it
+ * and invalidates the previous one (its later calls give undefined
+ * results), and calls of such contexts that overlap on one device race.
+ * The context is released with evlb_destroy as any other. */
+int evlb_init_noalloc(const evlb_params* params, void* hip_stream, evlb_ctx** out);
+
 /* Writes the reduced Maxwellian of the given node fields into d_f:
  * F_k = E_k(n, u, T) (Hermite expansion to order q-1), G_k = T E_k.
  * d_n, d_u, d_T: device [n_tot], read only.  d_f: device [2][q][n_tot].
- * dim 2: d_u is [2][n_tot], F_kl = n e_k(u_x) e_l(u_y) (the product of the
+ * dim 2: d_u is [2][n_tot], d_f is node-major [2][ny][nx][q][q] (see the
+ * layout notes above), F_kl = n e_k(u_x) e_l(u_y) (the product of the
  * unit-density expansions), G_kl = T/2 F_kl. */
 int evlb_set_equilibrium(evlb_ctx* ctx, const double* d_n, const double* d_u,
                          const double* d_T, double* d_f, void* hip_stream);

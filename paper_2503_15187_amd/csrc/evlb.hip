@@ -29,6 +29,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <type_traits>
 #include <vector>
@@ -2039,6 +2040,30 @@ bool device_matches(const evlb_ctx* c) {
 
 }  // namespace
 
+// The workspace of evlb_init_noalloc: one array per device, loaded with the
+// code object.  Host code reaches it only through the address that
+// hipGetSymbolAddress returns with that device current (the array's name in
+// host code is a host-side stand-in, not a device address).
+static __device__ __align__(256) unsigned char scratch[EVLB_NOALLOC_MAX_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch[kMaxDevices];  // device address of `scratch` per device (null: not looked up yet)
+
+int scratch_address(int device, void** out) {
+  if (device < 0 || device >= kMaxDevices) return EVLB_EHIP;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch[device]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return EVLB_EHIP;
+    g_scratch[device] = p;
+  }
+  *out = g_scratch[device];
+  return EVLB_OK;
+}
+}  // namespace
+
 extern "C" {
 
 int evlb_validate(const evlb_params* params) { return validate(params); }
@@ -2047,6 +2072,20 @@ size_t evlb_workspace_bytes(const evlb_params* params) {
   if (validate(params) != EVLB_OK) return 0;
   if (params->dim == 2) return evlb2d::workspace_bytes(params);
   return make_layout(params).total;
+}
+
+int evlb_init_noalloc(const evlb_params* params, void* hip_stream, evlb_ctx** out) {
+  if (!out) return EVLB_EINVAL;
+  *out = nullptr;
+  const int rc = validate(params);
+  if (rc) return rc;
+  if (evlb_workspace_bytes(params) > EVLB_NOALLOC_MAX_BYTES) return EVLB_EWORKSPACE;
+  int device = -1;
+  if (hipGetDevice(&device) != hipSuccess) return EVLB_EHIP;
+  void* ws = nullptr;
+  const int sc = scratch_address(device, &ws);
+  if (sc) return sc;
+  return evlb_init(params, ws, EVLB_NOALLOC_MAX_BYTES, hip_stream, out);
 }
 
 int evlb_init(const evlb_params* params, void* d_workspace, size_t ws_bytes, void* hip_stream, evlb_ctx** out) {

@@ -60,6 +60,8 @@ _SIGS = {
     "evlb_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(evlb_params)]),
     "evlb_init": (ctypes.c_int, [ctypes.POINTER(evlb_params), ctypes.c_void_p, ctypes.c_size_t,
                                  ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
+    "evlb_init_noalloc": (ctypes.c_int, [ctypes.POINTER(evlb_params), ctypes.c_void_p,
+                                         ctypes.POINTER(ctypes.c_void_p)]),
     "evlb_set_equilibrium": (ctypes.c_int, [ctypes.c_void_p] * 6),
     "evlb_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
     "evlb_rhs": (ctypes.c_int, [ctypes.c_void_p] * 4),
@@ -162,6 +164,18 @@ def evlb_init(params, workspace, stream=None):
     return out.value
 
 
+EVLB_NOALLOC_MAX_BYTES = 64 << 20
+
+
+def evlb_init_noalloc(params, stream=None):
+    """Returns a context handle (int) whose workspace is the library's static
+    device array (at most EVLB_NOALLOC_MAX_BYTES); a later noalloc context
+    on the same device invalidates it."""
+    out = ctypes.c_void_p()
+    _check(lib().evlb_init_noalloc(ctypes.byref(params), _stream(stream), ctypes.byref(out)), "evlb_init_noalloc")
+    return out.value
+
+
 def evlb_set_equilibrium(ctx, n, u, T, f, stream=None):
     _check(lib().evlb_set_equilibrium(ctx, _dptr(n, "n"), _dptr(u, "u"), _dptr(T, "T"), _dptr(f, "f"),
                                       _stream(stream)), "evlb_set_equilibrium")
@@ -228,7 +242,9 @@ class Solver:
     (u, q) carry an x and a y component; `planes` and `from_planes` convert
     to and from the per-velocity-plane view (2, q, q, ny, nx)."""
 
-    def __init__(self, q, dx, dt, nx, device=None, stream=None, **kw):
+    def __init__(self, q, dx, dt, nx, device=None, stream=None, noalloc=False, **kw):
+        """noalloc: the context uses the library's static workspace
+        (evlb_init_noalloc) instead of a workspace tensor."""
         self.params = make_params(q, dx, dt, nx, **kw)
         self.q = int(q)
         self.dim = int(self.params.dim)
@@ -238,8 +254,12 @@ class Solver:
             _check(evlb_validate(self.params) or EVLB_EINVAL, "evlb_workspace_bytes")
         device = device or torch.device("cuda", torch.cuda.current_device())
         self.device = device
-        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=device)
-        self.ctx = evlb_init(self.params, self.workspace, stream)
+        if noalloc:
+            self.workspace = None
+            self.ctx = evlb_init_noalloc(self.params, stream)
+        else:
+            self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=device)
+            self.ctx = evlb_init(self.params, self.workspace, stream)
         self.n_tot, self.velocities = evlb_info(self.ctx, self.q)
 
     def __del__(self):

@@ -174,3 +174,15 @@ def test_per_system_isothermal_temperatures():
     assert P.evlb_validate(P.make_params(16, 0.1, 5e-3, nxs, adjoint=1, T_iso_sys=[0.0] * 3)) == E.EVLB_OK
     with pytest.raises(ValueError):
         P.make_params(16, 0.1, 5e-3, nxs, T_iso_sys=[0.6, 0.6])
+
+
+def test_noalloc_rejects_oversized_workspace_on_host():
+    """evlb_init_noalloc checks the static workspace limit before any device
+    call: a 256 x 256 2D system needs more than EVLB_NOALLOC_MAX_BYTES."""
+    p = P.make_params(16, 0.25, DT2D, 256, ny=256)
+    assert P.evlb_workspace_bytes(p) > E.EVLB_NOALLOC_MAX_BYTES
+    out = ctypes.c_void_p()
+    assert P.lib().evlb_init_noalloc(ctypes.byref(p), None, ctypes.byref(out)) == E.EVLB_EWORKSPACE
+    assert out.value is None
+    cfl = P.make_params(16, 0.125, 0.1, 256)
+    assert P.lib().evlb_init_noalloc(ctypes.byref(cfl), None, ctypes.byref(out)) == E.EVLB_ECFL
