@@ -207,9 +207,10 @@ def write_traffic(workload, fetch_csv, write_csv, commands):
     write, wcal = per_kernel(write_csv, "WRITE_SIZE")
     sf, sw = 262144.0 / fcal, 262144.0 / wcal
     acc = defaultdict(lambda: [0.0, 0.0, 0])
-    ns = "evlb2d::" if workload.endswith("_2d") else "evlb::"  # the library's kernels of this dimension
+    two_d = workload.endswith("_2d")
     for raw, vals in fetch.items():
-        if ns not in raw:
+        # the library's kernels of this dimension (2D: namespace evlb2d)
+        if raw.startswith("__amd") or "at::" in raw or ("evlb2d::" in raw) != two_d:
             continue
         full, fam = _kernel_names(raw)
         wv = write.get(raw, {})
