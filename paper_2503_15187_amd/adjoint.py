@@ -6,7 +6,8 @@ sum_k p_k F_k through one node after every step.  The forward pass keeps a
 checkpoint every ceil(sqrt(nsteps)) steps.  The backward pass re-runs each
 segment from its checkpoint with evlb_step_record (states and stage states
 kept) and transposes it with evlb_adjoint_record, walking the segments in
-reverse; it returns the gradients with respect to the initial state and to
+reverse, the recomputation of the next segment on a second context and
+stream overlapping the transposition of the current one; it returns the gradients with respect to the initial state and to
 the parameters phi_sigma and sigma (the latter two enter as 0-d tensors whose
 values must equal the context's; they only carry the gradient).
 
@@ -68,11 +69,41 @@ class Rollout(torch.autograd.Function):
             obs[0, :, node] = ctx.vel
             w = g_flux.detach().contiguous()
         dparams = torch.zeros(2, dtype=torch.float64, device=lam.device)
-        rec = solver.record_buffer(every)
-        for start in sorted(ctx.ckpt, reverse=True):
+        # The segments in reverse.  The recomputation of segment i + 1 (a
+        # second context on a second stream, into the other record buffer)
+        # runs while segment i is transposed: the two chains of small
+        # launches fill the device together.
+        starts = sorted(ctx.ckpt, reverse=True)
+        recomp = getattr(solver, "_adjoint_twin", None)
+        if recomp is None:
+            recomp = solver._adjoint_twin = solver.twin()
+        recs = [solver.record_buffer(every), solver.record_buffer(every)]
+        main = torch.cuda.current_stream(lam.device)
+        side = torch.cuda.Stream(device=lam.device)
+        side.wait_stream(main)
+        ready = [torch.cuda.Event() for _ in starts]
+        freed = [torch.cuda.Event(), torch.cuda.Event()]
+
+        def recompute(i):
+            seg = min(every, nsteps - starts[i])
+            if i >= 2:
+                side.wait_event(freed[i % 2])  # segment i - 2 no longer reads this buffer
+            recomp.step_record(ctx.ckpt[starts[i]], seg, recs[i % 2], stream=side)
+            ready[i].record(side)
+
+        recompute(0)
+        if len(starts) > 1:
+            recompute(1)
+        for i, start in enumerate(starts):
             seg = min(every, nsteps - start)
-            solver.step_record(ctx.ckpt[start], seg, rec)
-            solver.adjoint_record(rec, seg, lam, dparams, obs, None if w is None else w[start:start + seg])
+            main.wait_event(ready[i])
+            solver.adjoint_record(recs[i % 2], seg, lam, dparams, obs, None if w is None else w[start:start + seg],
+                                  stream=main)
+            freed[i % 2].record(main)
+            if i + 2 < len(starts):
+                recompute(i + 2)
+        for r in recs:
+            r.record_stream(side)
         return lam, dparams[0], dparams[1], None, None, None, None
 
 

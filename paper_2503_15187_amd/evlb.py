@@ -246,6 +246,7 @@ class Solver:
         """noalloc: the context uses the library's static workspace
         (evlb_init_noalloc) instead of a workspace tensor."""
         self.params = make_params(q, dx, dt, nx, **kw)
+        self._args = (q, dx, dt, nx, dict(kw))
         self.q = int(q)
         self.dim = int(self.params.dim)
         self.shape2d = (int(self.params.ny), int(nx)) if self.dim == 2 else None
@@ -261,6 +262,13 @@ class Solver:
             self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=device)
             self.ctx = evlb_init(self.params, self.workspace, stream)
         self.n_tot, self.velocities = evlb_info(self.ctx, self.q)
+
+    def twin(self):
+        """A second context with the same parameters and its own workspace,
+        for work that runs concurrently with this one's on another stream
+        (a context's workspace serves one stream at a time)."""
+        q, dx, dt, nx, kw = self._args
+        return Solver(q, dx, dt, nx, device=self.device, **kw)
 
     def __del__(self):
         ctx = getattr(self, "ctx", None)
