@@ -369,11 +369,11 @@ __global__ __launch_bounds__(FNT) void fields_kernel(Dev D, const double* __rest
 //           wavefront 0 the raw velocity sums of row y - 2, 1 the Hermite
 //           coefficients a_m(u, T) of row y + 3, 2 the expansions e_k(u_x),
 //           e_l(u_y) of row y + 2 (one MFMA chain over 8 nodes x 2 axes), 3
-//           the per-node collision coefficients of row y + 3, 4 - 11
-//           (Dp x I) f of row y (v_mfma_f64_16x16x4 takes B element [c][col]
-//           from lane col + 16 c and returns row 4 j + c, column col in
-//           register j of that lane; col = (column, l parity)), 12 - 15 the
-//           strip-edge faces of row y.
+//           the per-node collision coefficients of row y + 3, 4 - 7 the
+//           strip-edge faces of row y, 8 - 15 (Dp x I) f of row y
+//           (v_mfma_f64_16x16x4 takes B element [c][col] from lane col + 16 c
+//           and returns row 4 j + c, column col in register j of that lane;
+//           col = (column, l parity)).
 // What one wavefront writes and another reads crosses exactly one barrier,
 // and every such buffer is double (quadruple for the collision
 // coefficients, read a full iteration after they are written), so that a
@@ -858,8 +858,9 @@ __global__ __launch_bounds__(SNT) void fused_kernel(Dev D, FusedArgs A, const do
         }
       }
     }
-    // the serial chains on the oldest wavefront of four SIMDs (the arbiter
-    // issues the oldest first), the MFMA and WENO work one or two per SIMD
+    // the serial chains on the oldest wavefront of each SIMD (the arbiter
+    // issues the oldest first), the strip-edge faces (VALU) on the next
+    // oldest, the MFMA work on the two youngest
     if (w == 0) {
       if (A.want_mom && y - 2 >= ya && L < nsum * SW) fused_raw_sum(D, A, S, d, L, x0, y - 2);
     } else if (w == 1) {
@@ -870,11 +871,11 @@ __global__ __launch_bounds__(SNT) void fused_kernel(Dev D, FusedArgs A, const do
     } else if (w == 3) {
       // collision coefficients of row y + 3
       if (y + 3 < yb && L < SW) fused_coeffs(D, S, (y + 3) & 1, (y + 3) & 3, L, d);
-    } else if (w < 12) {
+    } else if (w >= 8) {
       if (FRC && y < yb) {
-        // (Dp x I) f for l = 2 (w - 4) + lh: B[c][col16] = f(k = c + 4 b, l),
+        // (Dp x I) f for l = 2 (w - 8) + lh: B[c][col16] = f(k = c + 4 b, l),
         // col16 = (column, lh)
-        const int c4 = L >> 4, lq = 2 * (w - 4) + ((L >> 3) & 1);
+        const int c4 = L >> 4, lq = 2 * (w - 8) + ((L >> 3) & 1);
         dbl4 dd = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
         for (int b = 0; b < 4; ++b)
@@ -886,11 +887,11 @@ __global__ __launch_bounds__(SNT) void fused_kernel(Dev D, FusedArgs A, const do
           S.DX[yp][k][8 * (lq ^ (2 * (k & 1))) + col] = dd[j];
         }
       }
-    } else {
+    } else {  // wavefronts 4 - 7
       if (ADV && y < yb) {
         // the strip-edge face of velocity (k, l), q = 16 k + l, from the
         // interior columns 5 - 7 and the right halo of FI, into the owner's T
-        const int q = 64 * (w - 12) + L, k = q >> 4, l = q & 15;
+        const int q = 64 * (w - 4) + L, k = q >> 4, l = q & 15;
         const double* fi = &S.FI[yp][k][8 * l];
         const int sw = (l >> 1) & 7;
         const double i5 = fi[5 ^ sw], i6 = fi[6 ^ sw], i7 = fi[7 ^ sw];
