@@ -139,6 +139,10 @@ def host_cpu():
     return {"model": model, "cpus": len(os.sched_getaffinity(0))}
 
 
+TRAFFIC_SOURCE = ("profiles/hbm_traffic.txt: rocprofv3 FETCH_SIZE + WRITE_SIZE per launch from committed counter "
+                  "runs, used while the kernel source's sha256 matches (null otherwise); not counted in this run")
+
+
 def measured_traffic(workload, kernel):
     """HBM bytes per launch from the committed counter runs (profiles/
     hbm_traffic.txt), or None when the kernel's source file changed since."""
@@ -369,7 +373,7 @@ def measure_2d(E, torch, dev, steps, warmup):
             "ms_per_step": gpu_s * 1e3 / steps,
             "roofline": {"bound": "hbm", "kernel": "stage = " + " + ".join(KERNELS_2D), "achieved": achieved,
                          "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                         "traffic": None if None in traffic else sum(traffic),
+                         "traffic": None if None in traffic else sum(traffic), "traffic_source": TRAFFIC_SOURCE,
                          "bytes_per_stage": alg_stage, "avg_stage_us": stage_s * 1e6}}
 
 
@@ -558,8 +562,8 @@ def main():
         ent = {"config": {"workload": "slab_evaporation_1d", "nx": c["nx"], "q": c["Q"], "dx": c["dx"],
                           "dt": c["dt"], "T": c["T"], "exec": m["exec"], "tile_nodes": m["tile_nodes"]},
                "steps": args.slab_steps, "value": m["value"], "unit": "updates/s", "ms_per_step": m["ms_per_step"],
-               "roofline": dict(m["roofline"], traffic=measured_traffic("slab_evaporation_1d",
-                                                                          m["roofline"]["kernel"]))}
+               "roofline": dict(m["roofline"], traffic=measured_traffic("slab_evaporation_1d", m["roofline"]["kernel"]),
+                                traffic_source=TRAFFIC_SOURCE)}
         if not args.no_cpu_baseline:
             ent["cpu_baseline_1core"] = cpu_baseline(c, n, u, T)
         out["secondary"].append(ent)
@@ -577,7 +581,8 @@ def main():
             "config": {"workload": "batched_sweep_1d", "n_sys": cb["n_sys"], "n_tot": int(len(nb)), "q": cb["Q"],
                        "dx": cb["dx"], "exec": mb["exec"], "tile_nodes": mb["tile_nodes"]},
             "steps": args.batch_steps, "value": mb["value"], "unit": "updates/s", "ms_per_step": mb["ms_per_step"],
-            "roofline": dict(mb["roofline"], traffic=measured_traffic("batched_sweep_1d", mb["roofline"]["kernel"]))})
+            "roofline": dict(mb["roofline"], traffic=measured_traffic("batched_sweep_1d", mb["roofline"]["kernel"]),
+                             traffic_source=TRAFFIC_SOURCE)})
     if not args.no_adjoint:
         out["secondary"].append(adjoint_ratio(E, torch, dev, args.adjoint_steps))
     if not args.no_paper_runs:
