@@ -187,6 +187,27 @@ def test_steps_2d(nsteps):
     check(planes(f), [Fo, Go], 1e-11, steps=nsteps)
 
 
+@pytest.mark.parametrize("nx,ny,nsteps", [(37, 53, 2), (9, 8, 3)])
+def test_steps_2d_ragged_strips_and_segments(nx, ny, nsteps):
+    """Grids that the fused stage's 8-column strips and row segments do not
+    divide: 37 x 53 has a last strip of 5 columns and three row segments of
+    18, 18 and 17 rows; 9 x 8 has a strip of one column whose halo wraps
+    onto itself, at the smallest ny.  Right-hand side and steps against the
+    oracle."""
+    print(f"ragged 2d nx={nx} ny={ny} steps={nsteps}", flush=True)
+    c, n, ux, uy, T = small_case(nx, ny)
+    tb = tables(c)
+    F, G = oracle_state(c, n, ux, uy, T, tb)
+    s = solver(c, nx, ny)
+    LF, LG = step2d.rhs(F, G, tb)
+    check(planes(s.rhs(tstate(F, G))), [LF, LG], 1e-11, what="rhs")
+    Fo, Go = step2d.run(F, G, tb, nsteps)
+    f = tstate(F, G)
+    s.step(f, nsteps)
+    assert s.status() == E.EVLB_OK
+    check(planes(f), [Fo, Go], 1e-11, steps=nsteps, what="steps")
+
+
 def test_uniform_state_stationary_2d():
     c, n, ux, uy, T = workloads.phase_separation_2d(nx=48, ny=32)
     s = solver(c, 48, 32)
