@@ -456,12 +456,15 @@ __device__ __forceinline__ double weno5(double v0, double v1, double v2, double 
 }
 
 // Lane i of every 16-lane row takes lane i + 1's value (lane 15: 0).
-__device__ __forceinline__ double row_next(double v) {
+// DPP row_shl: lane i takes lane i + N of its row of 16 (0 past the row's end)
+template <int N>
+__device__ __forceinline__ double row_shl(double v) {
   const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
-  const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)b, 0x101, 0xf, 0xf, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), 0x101, 0xf, 0xf, false);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)b, 0x100 + N, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), 0x100 + N, 0xf, 0xf, false);
   return __builtin_bit_cast(double, (unsigned long long)(unsigned)lo | ((unsigned long long)(unsigned)hi << 32));
 }
+__device__ __forceinline__ double row_next(double v) { return row_shl<1>(v); }
 
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 
@@ -618,15 +621,16 @@ __global__ __launch_bounds__(SNT) void fused_kernel(Dev D, FusedArgs A, const do
   const unsigned rowf = (unsigned)nx * 8u;
   const double pk = velg[w];
   const double pxi = pk * D.inv_dx;
-  // MFMA A operand of the raw-sum weights of this wavefront's k: lane i + 16 c
-  // holds C[i][c + 4 b] for sum i (p = p_k, q = p_l):
+  // MFMA A operand of the raw-sum weights of this wavefront's k, for sums
+  // s < 8 over l < 8 in rows i = s and over l >= 8 in rows i = 8 + s: lane
+  // i + 16 c holds C[s][l = c + 4 b + 8 (i >> 3)] (p = p_k, q = p_l):
   //   F: n: 1, j_x: p, j_y: q, P_xx: p^2, P_xy: p q, P_yy: q^2,
   //      r_x: p (p^2 + q^2), r_y: q (p^2 + q^2);  G: g0: 1, h_x: p, h_y: q
-  double mop[4];
+  double mop[2];
 #pragma unroll
-  for (int b = 0; b < 4; ++b) {
-    const int i = L0 & 15;
-    const double q = velg[(L0 >> 4) + 4 * b], pq2 = pk * pk + q * q;
+  for (int b = 0; b < 2; ++b) {
+    const int i = L0 & 7;
+    const double q = velg[(L0 >> 4) + 4 * b + (L0 & 8)], pq2 = pk * pk + q * q;
     double cw = 0.0;
     if (i == 0) cw = 1.0;
     else if (i == 1) cw = pk;
@@ -787,21 +791,42 @@ __global__ __launch_bounds__(SNT) void fused_kernel(Dev D, FusedArgs A, const do
         }
       }
       double dy[2] = {0.0, 0.0};
-      if (FRC) {
-        // (I x Dp) f for k = w: B[c][col16] = f(w, l = c + 4 b) at column
-        // col16 & 7 (lanes with col16 >= 8 repeat columns 0 - 7); row l' =
-        // 4 j + c of the result from the lanes col16 < 8 to columns 14 - 21
+      const bool odd = ((y - ya) & 1) != 0;
+      if (FRC && (odd || y == yb - 1)) {
+        // (I x Dp) f for k = w of two rows at once: B[c][col16] = f(w, l =
+        // c + 4 b) at column col16 & 7 of row y - 1 (col16 < 8) or row y
+        // (col16 >= 8), both from this wavefront's interior of FI (the slot
+        // of row y - 1 is rewritten only in pre(y + 1)).  Row l' = 4 j + c of
+        // the result goes through columns 14 - 21 of T to the lanes that own
+        // it: row y's into this row's sum, row y - 1's (odd rows of the
+        // segment; the even rows before them ran no MFMA) into the sum of the
+        // row before.
         const int c4 = L >> 4, c8 = L & 7;
+        const bool hi = (L & 8) != 0;
+        const double* fp = &S.FI[hi ? yp : 1 - yp][w][0];
+        const int x = c8 ^ (c4 >> 1);  // the swizzle of l = c4 + 4 b is x ^ 2 b
         dbl4 dd = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
         for (int b = 0; b < 4; ++b)
-          dd = __builtin_amdgcn_mfma_f64_16x16x4f64(S.aop[b][L], Tw[(c4 + 4 * b) * TS + 3 + c8], dd, 0, 0, 0);
-        if ((L & 8) == 0) {
+          dd = __builtin_amdgcn_mfma_f64_16x16x4f64(S.aop[b][L], fp[8 * (c4 + 4 * b) + (x ^ (2 * b))], dd, 0, 0, 0);
+        if (hi) {
 #pragma unroll
           for (int j = 0; j < 4; ++j) Tw[(4 * j + c4) * TS + 14 + c8] = dd[j];
         }
 #pragma unroll
         for (int j = 0; j < 2; ++j) dy[j] = Tw[(r + 8 * j) * TS + 14 + col];
+        if (odd) {
+          if (!hi) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) Tw[(4 * j + c4) * TS + 14 + c8] = dd[j];
+          }
+          // the lanes that wrote nothing still read what the others wrote:
+          // keep the compiler from reusing the values read above
+          asm volatile("" ::: "memory");
+          const double fyp = A.c * S.CF[(y - 1) & 3][CF_FY][col];
+#pragma unroll
+          for (int j = 0; j < 2; ++j) accP[j] = fma(-fyp, Tw[(r + 8 * j) * TS + 14 + col], accP[j]);
+        }
       }
       // collision terms: with xi_x = p_k - u_x fixed per wavefront, the row
       // polynomial in xi_y = p_l - u_y
@@ -846,15 +871,18 @@ __global__ __launch_bounds__(SNT) void fused_kernel(Dev D, FusedArgs A, const do
       if (live && A.want_mom) {
         // this wavefront's terms of the raw sums, C f^(s) with C[s][l] the
         // weights of sum s (mop), on the MFMA: B[c][col16] = f^(s)(w, l =
-        // c + 4 b) at column col16 & 7, rows s = 4 j + c of the result
+        // c + 4 b + 8 h) at column col16 & 7, h = col16 >> 3.  Sum s = 4 j + c
+        // of a column is row s of the result at col16 < 8 (over l < 8) plus
+        // row 8 + s at col16 + 8 (over l >= 8), eight lanes further.
         const int c4 = L >> 4, c8 = L & 7;
         dbl4 dd = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int b = 0; b < 4; ++b)
-          dd = __builtin_amdgcn_mfma_f64_16x16x4f64(mop[b], Tw[(c4 + 4 * b) * TS + 14 + c8], dd, 0, 0, 0);
+        for (int b = 0; b < 2; ++b)
+          dd = __builtin_amdgcn_mfma_f64_16x16x4f64(mop[b], Tw[(c4 + 4 * b + (L & 8)) * TS + 14 + c8], dd, 0, 0, 0);
+        const double s0 = dd[0] + row_shl<8>(dd[2]), s1 = dd[1] + row_shl<8>(dd[3]);
         if ((L & 8) == 0) {
-          S.mred[pb][w][c4][c8] = dd[0];
-          S.mred[pb][w][4 + c4][c8] = dd[1];
+          S.mred[pb][w][c4][c8] = s0;
+          S.mred[pb][w][4 + c4][c8] = s1;
         }
       }
     }
