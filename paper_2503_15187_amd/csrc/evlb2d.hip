@@ -426,37 +426,40 @@ struct FusedSmem {
 static_assert(sizeof(FusedSmem) <= 160 * 1024, "fused stage LDS exceeds 160 KiB");
 
 // WENO-5 (Jiang & Shu) value at a face from the five values v0 .. v4 ordered
-// from the upwind side (v2 is the node upwind of the face).  Candidates
-// c_r, smoothness 12 beta_r = 13 a_r^2 + 3 b_r^2, weights d_r / (eps +
-// beta_r)^2 normalised: with t_r = (12 eps + 12 beta_r)^2 and 10 d = (1, 6, 3)
-// the value is (t1 t2 c0 + 6 t0 t2 c1 + 3 t0 t1 c2) / (t1 t2 + 6 t0 t2 +
-// 3 t0 t1) (every common factor cancels); 6 c1 and 3 c2 are formed directly.
-// The division goes through a hardware reciprocal refined by two Newton
-// steps.
+// from the upwind side (v2 is the node upwind of the face), written in the
+// first differences e_m = v_(m+1) - v_m.  The candidates less v2 are g0 =
+// (5 e1 - 2 e0) / 6, 6 g1 = e1 + 2 e2, 3 g2 = 2 e2 - e3 / 2; the
+// smoothness 12 beta_r = 13 a_r^2 + 3 b_r^2 expands in the squares and
+// neighbour products of the differences to 16 e0^2 - 44 e0 e1 + 40 e1^2,
+// 16 e1^2 - 20 e1 e2 + 16 e2^2 and 40 e2^2 - 44 e2 e3 + 16 e3^2.  The weights
+// d_r / (eps + beta_r)^2 normalised: with t_r = (12 eps + 12 beta_r)^2 and
+// 10 d = (1, 6, 3) the value is v2 + (t1 t2 g0 + 6 t0 t2 g1 + 3 t0 t1 g2) /
+// (t1 t2 + 6 t0 t2 + 3 t0 t1) (every common factor cancels).  The division
+// goes through a hardware reciprocal refined by two Newton steps.
 __device__ __forceinline__ double weno5(double v0, double v1, double v2, double v3, double v4, double eps12) {
-  const double c0 = fma(1.0 / 3.0, v0, fma(-7.0 / 6.0, v1, (11.0 / 6.0) * v2));
-  const double c1x6 = fma(5.0, v2, fma(2.0, v3, -v1));
-  const double c2x3 = fma(2.5, v3, fma(-0.5, v4, v2));
-  const double a0 = fma(-2.0, v1, v0 + v2), b0 = fma(-4.0, v1, fma(3.0, v2, v0));
-  const double a1 = fma(-2.0, v2, v1 + v3), b1 = v1 - v3;
-  const double a2 = fma(-2.0, v3, v2 + v4), b2 = fma(-4.0, v3, fma(3.0, v2, v4));
-  double t0 = fma(13.0 * a0, a0, fma(3.0 * b0, b0, eps12));
-  double t1 = fma(13.0 * a1, a1, fma(3.0 * b1, b1, eps12));
-  double t2 = fma(13.0 * a2, a2, fma(3.0 * b2, b2, eps12));
+  const double e0 = v1 - v0, e1 = v2 - v1, e2 = v3 - v2, e3 = v4 - v3;
+  const double s0 = e0 * e0, s1 = e1 * e1, s2 = e2 * e2, s3 = e3 * e3;
+  const double x01 = e0 * e1, x12 = e1 * e2, x23 = e2 * e3;
+  double t0 = fma(16.0, s0, fma(-44.0, x01, fma(40.0, s1, eps12)));
+  double t1 = fma(16.0, s1, fma(-20.0, x12, fma(16.0, s2, eps12)));
+  double t2 = fma(40.0, s2, fma(-44.0, x23, fma(16.0, s3, eps12)));
   t0 *= t0;
   t1 *= t1;
   t2 *= t2;
   const double u0 = t1 * t2, u1 = t0 * t2, u2 = t0 * t1;
-  const double num = fma(u2, c2x3, fma(u1, c1x6, u0 * c0));
+  const double g0 = fma(5.0 / 6.0, e1, (-1.0 / 3.0) * e0);
+  const double g1x6 = fma(2.0, e2, e1);
+  const double g2x3 = fma(2.0, e2, -0.5 * e3);
+  const double num = fma(u2, g2x3, fma(u1, g1x6, u0 * g0));
   const double den = fma(3.0, u2, fma(6.0, u1, u0));
   double r = __builtin_amdgcn_rcp(den);
   r = fma(r, fma(-den, r, 1.0), r);
   r = fma(r, fma(-den, r, 1.0), r);
-  return num * r;
+  return fma(num, r, v2);
 }
 
-// Lane i of every 16-lane row takes lane i + 1's value (lane 15: 0).
-// DPP row_shl: lane i takes lane i + N of its row of 16 (0 past the row's end)
+// DPP row_shl: lane i of every 16-lane row takes lane i + N's value (0 past
+// the row's end)
 template <int N>
 __device__ __forceinline__ double row_shl(double v) {
   const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
