@@ -100,53 +100,63 @@ __device__ __forceinline__ double rcpn(double x) {
 // values v0..v4 = f_{i-2}..f_{i+2}; alpha_r = d_r/(eps+beta_r)^2 combined
 // over a common denominator (one reciprocal).
 //
-// Two arithmetic forms of the same function.  LEAN takes common factors out
-// where they cancel -- the candidates are formed as 6 q_r, the smoothness
-// indicators as 12 beta_r against 12 eps, the linear weights as
-// 10 d_r = (1, 6, 3), and 1/6 is applied once beside the reciprocal -- for
-// about ten fewer operations per face: the column and wide tiles, whose
-// faces are throughput work, use it.  The narrow tile's faces sit on its
-// critical path, and there the textbook form measures slightly faster.
+// Two arithmetic forms of the same function.  LEAN works in the first
+// differences e_m = v_(m+1) - v_m: the candidates less v2 are g0 = (5 e1 -
+// 2 e0) / 6, 6 g1 = e1 + 2 e2, 3 g2 = 2 e2 - e3 / 2; the smoothness
+// indicators 12 beta_r (against 12 eps) expand in the squares and neighbour
+// products of the differences to 16 e0^2 - 44 e0 e1 + 40 e1^2, 16 e1^2 -
+// 20 e1 e2 + 16 e2^2 and 40 e2^2 - 44 e2 e3 + 16 e3^2; with the linear
+// weights as 10 d_r = (1, 6, 3) the value is v2 plus the normalised
+// weighted corrections -- about fifteen fewer operations per face: the
+// column and wide tiles, whose faces are throughput work, use it.  The
+// narrow tile's faces sit on its critical path, and there the textbook form
+// measures slightly faster.
 template <bool LEAN>
 __device__ __forceinline__ double weno5(double v0, double v1, double v2, double v3, double v4,
                                         double eps) {
+  if constexpr (LEAN) {
+    const double eps12 = 12.0 * eps;
+    const double d0 = v1 - v0, d1 = v2 - v1, d2 = v3 - v2, d3 = v4 - v3;
+    const double s0 = d0 * d0, s1 = d1 * d1, s2 = d2 * d2, s3 = d3 * d3;
+    const double x01 = d0 * d1, x12 = d1 * d2, x23 = d2 * d3;
+    double t0 = fma(16.0, s0, fma(-44.0, x01, fma(40.0, s1, eps12)));
+    double t1 = fma(16.0, s1, fma(-20.0, x12, fma(16.0, s2, eps12)));
+    double t2 = fma(40.0, s2, fma(-44.0, x23, fma(16.0, s3, eps12)));
+    t0 *= t0;
+    t1 *= t1;
+    t2 *= t2;
+    const double u0 = t1 * t2, u1 = t0 * t2, u2 = t0 * t1;
+    const double g0 = fma(5.0 / 6.0, d1, (-1.0 / 3.0) * d0);
+    const double g1x6 = fma(2.0, d2, d1);
+    const double g2x3 = fma(2.0, d2, -0.5 * d3);
+    const double num = fma(u2, g2x3, fma(u1, g1x6, u0 * g0));
+    const double den = fma(3.0, u2, fma(6.0, u1, u0));
+    double r = __builtin_amdgcn_rcp(den);
+    r = fma(r, fma(-den, r, 1.0), r);
+    r = fma(r, fma(-den, r, 1.0), r);
+    return fma(num, r, v2);
+  }
   const double c0 = v0 - 2.0 * v1 + v2, e0 = v0 - 4.0 * v1 + 3.0 * v2;
   const double c1 = v1 - 2.0 * v2 + v3, e1 = v1 - v3;
   const double c2 = v2 - 2.0 * v3 + v4, e2 = 3.0 * v2 - 4.0 * v3 + v4;
-  double q0, q1, q2, w0, w1, w2;
-  if constexpr (LEAN) {
-    q0 = 2.0 * v0 - 7.0 * v1 + 11.0 * v2;
-    q1 = -v1 + 5.0 * v2 + 2.0 * v3;
-    q2 = 2.0 * v2 + 5.0 * v3 - v4;
-    const double eps12 = 12.0 * eps;
-    double t0 = fma(13.0 * c0, c0, fma(3.0 * e0, e0, eps12)); t0 *= t0;
-    double t1 = fma(13.0 * c1, c1, fma(3.0 * e1, e1, eps12)); t1 *= t1;
-    double t2 = fma(13.0 * c2, c2, fma(3.0 * e2, e2, eps12)); t2 *= t2;
-    w0 = t1 * t2;
-    w1 = 6.0 * t0 * t2;
-    w2 = 3.0 * t0 * t1;
-  } else {
-    q0 = (2.0 * v0 - 7.0 * v1 + 11.0 * v2) * (1.0 / 6.0);
-    q1 = (-v1 + 5.0 * v2 + 2.0 * v3) * (1.0 / 6.0);
-    q2 = (2.0 * v2 + 5.0 * v3 - v4) * (1.0 / 6.0);
-    const double b0 = (13.0 / 12.0) * c0 * c0 + 0.25 * e0 * e0;
-    const double b1 = (13.0 / 12.0) * c1 * c1 + 0.25 * e1 * e1;
-    const double b2 = (13.0 / 12.0) * c2 * c2 + 0.25 * e2 * e2;
-    double t0 = eps + b0; t0 *= t0;
-    double t1 = eps + b1; t1 *= t1;
-    double t2 = eps + b2; t2 *= t2;
-    w0 = 0.1 * t1 * t2;
-    w1 = 0.6 * t0 * t2;
-    w2 = 0.3 * t0 * t1;
-  }
+  const double q0 = (2.0 * v0 - 7.0 * v1 + 11.0 * v2) * (1.0 / 6.0);
+  const double q1 = (-v1 + 5.0 * v2 + 2.0 * v3) * (1.0 / 6.0);
+  const double q2 = (2.0 * v2 + 5.0 * v3 - v4) * (1.0 / 6.0);
+  const double b0 = (13.0 / 12.0) * c0 * c0 + 0.25 * e0 * e0;
+  const double b1 = (13.0 / 12.0) * c1 * c1 + 0.25 * e1 * e1;
+  const double b2 = (13.0 / 12.0) * c2 * c2 + 0.25 * e2 * e2;
+  double t0 = eps + b0; t0 *= t0;
+  double t1 = eps + b1; t1 *= t1;
+  double t2 = eps + b2; t2 *= t2;
+  const double w0 = 0.1 * t1 * t2;
+  const double w1 = 0.6 * t0 * t2;
+  const double w2 = 0.3 * t0 * t1;
   // divide through the hardware reciprocal and two Newton steps r <- r (2 - d r)
   const double den = w0 + w1 + w2;
   double r = __builtin_amdgcn_rcp(den);
   r = fma(r, fma(-den, r, 1.0), r);
   r = fma(r, fma(-den, r, 1.0), r);
-  double num = w0 * q0 + w1 * q1 + w2 * q2;
-  if constexpr (LEAN) num *= 1.0 / 6.0;
-  return num * r;
+  return (w0 * q0 + w1 * q1 + w2 * q2) * r;
 }
 
 // Launch shape of the wide stage kernel: tiles of W = 64 nodes, NG groups of
