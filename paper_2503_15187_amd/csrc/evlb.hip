@@ -117,11 +117,14 @@ __device__ __forceinline__ double weno5(double v0, double v1, double v2, double 
   if constexpr (LEAN) {
     const double eps12 = 12.0 * eps;
     const double d0 = v1 - v0, d1 = v2 - v1, d2 = v3 - v2, d3 = v4 - v3;
-    const double s0 = d0 * d0, s1 = d1 * d1, s2 = d2 * d2, s3 = d3 * d3;
+    // eps12 enters through the squares: -eps12 / 64 on the outer two, eps12 / 32
+    // on the inner two sum to eps12 in every indicator (no accumulator copy)
+    const double lo = -eps12 * (1.0 / 64.0), hi = eps12 * (1.0 / 32.0);
+    const double s0 = fma(d0, d0, lo), s1 = fma(d1, d1, hi), s2 = fma(d2, d2, hi), s3 = fma(d3, d3, lo);
     const double x01 = d0 * d1, x12 = d1 * d2, x23 = d2 * d3;
-    double t0 = fma(16.0, s0, fma(-44.0, x01, fma(40.0, s1, eps12)));
-    double t1 = fma(16.0, s1, fma(-20.0, x12, fma(16.0, s2, eps12)));
-    double t2 = fma(40.0, s2, fma(-44.0, x23, fma(16.0, s3, eps12)));
+    double t0 = fma(16.0, s0, fma(-44.0, x01, 40.0 * s1));
+    double t1 = fma(16.0, s1, fma(-20.0, x12, 16.0 * s2));
+    double t2 = fma(40.0, s2, fma(-44.0, x23, 16.0 * s3));
     t0 *= t0;
     t1 *= t1;
     t2 *= t2;

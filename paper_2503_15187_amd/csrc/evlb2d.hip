@@ -438,11 +438,14 @@ static_assert(sizeof(FusedSmem) <= 160 * 1024, "fused stage LDS exceeds 160 KiB"
 // goes through a hardware reciprocal refined by two Newton steps.
 __device__ __forceinline__ double weno5(double v0, double v1, double v2, double v3, double v4, double eps12) {
   const double e0 = v1 - v0, e1 = v2 - v1, e2 = v3 - v2, e3 = v4 - v3;
-  const double s0 = e0 * e0, s1 = e1 * e1, s2 = e2 * e2, s3 = e3 * e3;
+  // eps12 enters through the squares: -eps12 / 64 on the outer two, eps12 / 32
+  // on the inner two sum to eps12 in every indicator (no accumulator copy)
+  const double lo = -eps12 * (1.0 / 64.0), hi = eps12 * (1.0 / 32.0);
+  const double s0 = fma(e0, e0, lo), s1 = fma(e1, e1, hi), s2 = fma(e2, e2, hi), s3 = fma(e3, e3, lo);
   const double x01 = e0 * e1, x12 = e1 * e2, x23 = e2 * e3;
-  double t0 = fma(16.0, s0, fma(-44.0, x01, fma(40.0, s1, eps12)));
-  double t1 = fma(16.0, s1, fma(-20.0, x12, fma(16.0, s2, eps12)));
-  double t2 = fma(40.0, s2, fma(-44.0, x23, fma(16.0, s3, eps12)));
+  double t0 = fma(16.0, s0, fma(-44.0, x01, 40.0 * s1));
+  double t1 = fma(16.0, s1, fma(-20.0, x12, 16.0 * s2));
+  double t2 = fma(40.0, s2, fma(-44.0, x23, 16.0 * s3));
   t0 *= t0;
   t1 *= t1;
   t2 *= t2;
