@@ -26,6 +26,7 @@
 #include "evlb2d.h"
 
 #include <cmath>
+#include <cstddef>
 #include <cstdint>
 #include <cstring>
 #include <new>
@@ -575,6 +576,11 @@ __device__ __forceinline__ void fused_raw_sum(const Dev& D, const FusedArgs& A, 
   A.raw[(long long)((d == 0 ? 0 : 8) + s) * D.ntot + (long long)y * D.nx + x0 + cc] = (v[0] + v[1]) + (v[2] + v[3]);
 }
 
+template <int N>
+struct RotC {
+  static constexpr int value = N;
+};
+
 template <bool ADV, bool FRC, bool FIRST>
 __global__ __launch_bounds__(SNT) void fused_kernel(Dev D, FusedArgs A, const double* __restrict__ velg,
                                                     const double* __restrict__ meqg,
@@ -703,7 +709,34 @@ __global__ __launch_bounds__(SNT) void fused_kernel(Dev D, FusedArgs A, const do
 
   const int nsum = d == 0 ? 8 : 3;
   double accP[2] = {0.0, 0.0}, cfxP = 0.0;  // acc and c F_x of the row before
-  for (int y = ya; y <= yb; ++y) {
+  // Byte offsets in the shared block of this lane's writes of row y into FI
+  // (slot 0; l = r, r + 8) and of its halo values into T and FI, formed once
+  // and held opaque, so that the compiler keeps them in registers instead of
+  // deriving them again every row.
+  unsigned ofi[2], oh[4];
+  {
+    const int r0 = L0 >> 3, c0 = L0 & 7;
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int l = r0 + 8 * j;
+      ofi[j] = (unsigned)offsetof(FusedSmem, FI) + 8u * (unsigned)(w * FIS + 8 * l + (c0 ^ ((l >> 1) & 7)));
+    }
+    const int lA = L0 >> 2, hA = L0 & 3, lB = (L0 & 31) >> 1, hB = 4 + (L0 & 1);
+    oh[0] = (unsigned)offsetof(FusedSmem, T) + 8u * (unsigned)((16 * w + lA) * TS + (hA < 3 ? hA : SW + hA));
+    oh[1] = (unsigned)offsetof(FusedSmem, FI) + 8u * (unsigned)(w * FIS + 16 * SW + 3 * lA);
+    oh[2] = (unsigned)offsetof(FusedSmem, T) + 8u * (unsigned)((16 * w + lB) * TS + SW + hB);
+    oh[3] = (unsigned)offsetof(FusedSmem, FI) + 8u * (unsigned)(w * FIS + 16 * SW + 3 * lB + hB - 3);
+  }
+  asm volatile("" : "+v"(ofi[0]), "+v"(ofi[1]), "+v"(oh[0]), "+v"(oh[1]), "+v"(oh[2]), "+v"(oh[3]));
+  char* const Sb = (char*)&S;
+  auto lds = [&](unsigned o) -> double& { return *(double*)(Sb + o); };
+  // One row of the march.  The ring is not shifted: row y uses the slots
+  // rotated by ROT = (y - ya) mod 5 (slot (i + ROT) mod 5 holds ring entry
+  // i), and the march is unrolled five rows at a time so that every slot
+  // index is a constant.
+  auto row = [&](auto rotc, const int y) {
+    constexpr int ROT = decltype(rotc)::value;
+    auto R = [&](int j, int i) -> double& { return R5[j][(i + ROT) % 5]; };
     // Opaque per-row copies of the thread indices: every LDS address and
     // table value below is derived from them inside the row, so that the
     // compiler does not hoist them out of the loop and hold (or spill) them
@@ -718,42 +751,29 @@ __global__ __launch_bounds__(SNT) void fused_kernel(Dev D, FusedArgs A, const do
     const double* cf = &S.CF[y & 3][0][col];
     double part[2] = {0.0, 0.0}, base[2] = {0.0, 0.0};
     if (y < yb) {
-      if (y > ya) {
-        // advance the ring: the row loaded into R0 last row moves to the end
-#pragma unroll
-        for (int j = 0; j < 2; ++j) {
-          const double t = R5[j][0];
-          R5[j][0] = R5[j][1];
-          R5[j][1] = R5[j][2];
-          R5[j][2] = R5[j][3];
-          R5[j][3] = R5[j][4];
-          R5[j][4] = t;
-        }
-      }
-      double* fi = &S.FI[yp][w][0];
+      const unsigned fslot = (unsigned)yp * (unsigned)(Q * FIS * 8);  // FI[yp]
       const double nu = cf[CF_NU * SW];
       double cur[2];
-      cur[0] = R5[0][1];  // row y
-      cur[1] = R5[1][2];
+      cur[0] = R(0, 1);  // row y
+      cur[1] = R(1, 2);
 #pragma unroll
       for (int j = 0; j < 2; ++j) {
         Tw[(r + 8 * j) * TS + 3 + col] = cur[j];
-        fi[8 * (r + 8 * j) + (col ^ (((r + 8 * j) >> 1) & 7))] = cur[j];
+        lds(ofi[j] + fslot) = cur[j];  // FI[yp][w][8 l + (col ^ ((l >> 1) & 7))]
         base[j] = fma(A.a, f0v[j], bb * cur[j]);
         part[j] = -nu * cur[j];
       }
-      {
-        const int lA = L >> 2, hA = L & 3, lB = (L & 31) >> 1, hB = 4 + (L & 1);
-        Tw[lA * TS + (hA < 3 ? hA : SW + hA)] = hv[0];
-        if (hA == 3) fi[16 * SW + 3 * lA] = hv[0];
-        Tw[lB * TS + SW + hB] = hv[1];
-        fi[16 * SW + 3 * lB + hB - 3] = hv[1];
-      }
+      // the halo: T of columns x0 - 3 .. x0 - 1, x0 + 8 .. x0 + 10, FI of
+      // columns x0 + 8 .. x0 + 10
+      lds(oh[0]) = hv[0];
+      if ((L & 3) == 3) lds(oh[1] + fslot) = hv[0];
+      lds(oh[2]) = hv[1];
+      lds(oh[3] + fslot) = hv[1];
       if (tid < NF * SW) S.fl[(y + 3) & 1][tid / SW][tid & (SW - 1)] = fq;
       if (ADV) {
         // y faces: j = 0 upwind from above, j = 1 from below
-        const double fyr0 = weno5(R5[0][4], R5[0][3], R5[0][2], R5[0][1], R5[0][0], eps12);
-        const double fyr1 = weno5(R5[1][0], R5[1][1], R5[1][2], R5[1][3], R5[1][4], eps12);
+        const double fyr0 = weno5(R(0, 4), R(0, 3), R(0, 2), R(0, 1), R(0, 0), eps12);
+        const double fyr1 = weno5(R(1, 0), R(1, 1), R(1, 2), R(1, 3), R(1, 4), eps12);
         part[0] = fma(D.inv_dx * S.vel[r], fyl[0] - fyr0, part[0]);
         part[1] = fma(D.inv_dx * S.vel[r + 8], fyl[1] - fyr1, part[1]);
         fyl[0] = fyr0;
@@ -769,7 +789,7 @@ __global__ __launch_bounds__(SNT) void fused_kernel(Dev D, FusedArgs A, const do
     // load in flight.
     fq = bload(rf, fvo, rowsf(y + 4));
 #pragma unroll
-    for (int j = 0; j < 2; ++j) R5[j][0] = bload(rs, vo, j * pso + rowso(y + 4 - j));  // row (y + 1) + 3 - j
+    for (int j = 0; j < 2; ++j) R(j, 0) = bload(rs, vo, j * pso + rowso(y + 4 - j));  // row (y + 1) + 3 - j
     {
       const unsigned so1 = rowso(y + 1);
       if (!FIRST) {
@@ -938,6 +958,17 @@ __global__ __launch_bounds__(SNT) void fused_kernel(Dev D, FusedArgs A, const do
 #pragma unroll
     for (int j = 0; j < 2; ++j) accP[j] = accN[j];
     cfxP = cfxN;
+  };
+  for (int y = ya; y <= yb; y += 5) {
+    row(RotC<0>(), y);
+    if (y + 1 > yb) break;
+    row(RotC<1>(), y + 1);
+    if (y + 2 > yb) break;
+    row(RotC<2>(), y + 2);
+    if (y + 3 > yb) break;
+    row(RotC<3>(), y + 3);
+    if (y + 4 > yb) break;
+    row(RotC<4>(), y + 4);
   }
   // velocity sums of the last row
   __syncthreads();
