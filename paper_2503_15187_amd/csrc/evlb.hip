@@ -96,6 +96,16 @@ __device__ __forceinline__ double rcpn(double x) {
   return fma(r, fma(-x, r, 1.0), r);
 }
 
+// Lane i takes lane i + 1's value across the whole wavefront (DPP wave_shl:1;
+// lane 63 gets 0).  Two VALU moves, where a shuffle is an LDS-crossbar round
+// trip.
+__device__ __forceinline__ double wave_next(double v) {
+  const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)b, 0x130, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), 0x130, 0xf, 0xf, false);
+  return __builtin_bit_cast(double, (unsigned long long)(unsigned)lo | ((unsigned long long)(unsigned)hi << 32));
+}
+
 // Classical WENO-5 (Jiang & Shu) face value from the five upwind-ordered
 // values v0..v4 = f_{i-2}..f_{i+2}; alpha_r = d_r/(eps+beta_r)^2 combined
 // over a common denominator (one reciprocal).
@@ -1288,8 +1298,8 @@ __device__ void stage_tile_col(const DevParams& P, const StageArgs& A, int tile,
       const double* gr = &S.f[Q + k][0];
       const double hF = weno5<true>(fr[b0], fr[b0 + st], fr[b0 + 2 * st], fr[b0 + 3 * st], fr[b0 + 4 * st], P.weno_eps);
       const double hG = weno5<true>(gr[b0], gr[b0 + st], gr[b0 + 2 * st], gr[b0 + 3 * st], gr[b0 + 4 * st], P.weno_eps);
-      const double hFr = __shfl_down(hF, 1);
-      const double hGr = __shfl_down(hG, 1);
+      const double hFr = wave_next(hF);  // lane 63's faces are not used
+      const double hGr = wave_next(hG);
       LF = -pk * (hFr - hF) * P.inv_dx;
       LG = -pk * (hGr - hG) * P.inv_dx;
     }
