@@ -358,9 +358,11 @@ __global__ __launch_bounds__(FNT) void fields_kernel(Dev D, const double* __rest
 //           WENO-5 faces along y from a ring of five rows per velocity in
 //           registers; WENO-5 faces along x from the LDS row (each lane the
 //           face on its left, the one on its right from the next lane by
-//           DPP); (I x Dp) f on the f64 MFMA; the Shakhov + J1 collision
-//           terms as a polynomial in xi_x and xi_y per node; everything but
-//           the (Dp x I) f term and the strip-edge face folded into acc(y).
+//           DPP); (I x Dp) f on the f64 MFMA, every other row for that row
+//           and the one before it (whose term goes into acc(y - 1)); the
+//           Shakhov + J1 collision terms as a polynomial in xi_x and xi_y per
+//           node; everything but the (Dp x I) f term and the strip-edge face
+//           folded into acc(y).
 //  barrier
 //  post(y)  the work that reads other wavefronts' rows or writes what they
 //           read: f^(s) of row y - 1 from acc(y - 1), the (Dp x I) f term and
