@@ -338,9 +338,10 @@ KERNELS_2D = ("fields_kernel", "fused_kernel")
 def measure_2d(E, torch, dev, steps, warmup):
     """2D phase separation: 1024 x 1024 periodic nodes, dx = sigma/4, 16 x 16
     tensor Gauss-Hermite velocities plus the reduced z-energy, T = 0.75 T_c
-    of the disc kernel, n0 = 0.3 with 1% Gaussian noise.  One RK stage is three
-    launches (node fields, advection, velocity space); the roofline is taken
-    over the stage: algorithmic bytes per stage / stage time."""
+    of the disc kernel, n0 = 0.3 with 1% Gaussian noise.  One RK stage is two
+    launches (node fields, then the fused stage kernel), and one raw-sums
+    launch starts each evlb_step call; the roofline is taken over the stage:
+    algorithmic bytes per stage / stage time."""
     import workloads
     c, n, ux, uy, T = workloads.phase_separation_2d()
     td = lambda a: torch.tensor(a, dtype=torch.float64, device=dev)
